@@ -1,0 +1,210 @@
+/*
+ * GRIM-Filter CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the library or its Python binding may
+ * load, link or call this code. Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg use it, to check and to time against.
+ *
+ * It computes, with plain loops and no blocking or bit tricks, the exact
+ * integer result that GRIM-Filter defines (Kim et al., "GRIM-Filter: Fast seed
+ * location filtering in DNA read mapping using processing-in-memory
+ * technologies", arXiv 1708.04329):
+ *
+ *   Section 3, bit vector generation: the reference is cut into bins; bin x
+ *     has one existence bit per possible token (q-gram), set when a token
+ *     whose FIRST base lies in bin x occurs there. Bins overlap so that a read
+ *     starting in bin x lies wholly inside it.
+ *   Section 6.1: a bit vector holds 4^q bits (4^5 = 1024 for q = 5).
+ *   Section 3, steps 1-3: a read's tokens are extracted, their existence bits
+ *     in a bin are summed, and the bin passes when the sum meets a threshold.
+ *   Section 3, threshold: an exact match yields read_length - (q - 1) tokens;
+ *     each error can destroy up to q tokens, so with E errors the threshold is
+ *     (L - q + 1) - q*E.
+ *   Section 6, caption of the read-existence figure: E is the ceiling of the
+ *     read length times the error tolerance e.
+ *   Section 3, steps 4-5: a candidate location is checked against the bit of
+ *     the bin holding its first base.
+ *
+ * Conventions the paper leaves open (each one is listed with its reading in
+ * the design notes; the GPU path implements the same reading independently):
+ *   - bins are B bases wide; bin x is extended by O bases into the next bin:
+ *     token starts s with x*B <= s < min(x*B + B + O, G - q + 1) count for bin x;
+ *     the number of bins is ceil(G / B); the last bin is partial;
+ *   - token code: A=0, C=1, G=2, T=3 (case-insensitive), first base most
+ *     significant; any other byte makes the window invalid: an invalid
+ *     reference window sets no bit, an invalid read window adds 0 but still
+ *     counts in L - q + 1;
+ *   - every token occurrence of a read counts (repeated tokens add again);
+ *   - pass means count >= T; T <= 0 passes every bin;
+ *   - E = ceil(e_permille * L / 1000) in integer arithmetic, unless an explicit
+ *     per-read E is given.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+/* Base code of one reference or read byte; -1 for anything but A, C, G, T. */
+static int base_code(uint8_t c) {
+  switch (c) {
+    case 'A': case 'a': return 0;
+    case 'C': case 'c': return 1;
+    case 'G': case 'g': return 2;
+    case 'T': case 't': return 3;
+    default: return -1;
+  }
+}
+
+/* Token (q-gram) code of s[0..q): sum of code(s[j]) * 4^(q-1-j); -1 if invalid. */
+int64_t oracle_token_code(const uint8_t* s, uint32_t q) {
+  int64_t code = 0;
+  for (uint32_t j = 0; j < q; ++j) {
+    int c = base_code(s[j]);
+    if (c < 0) return -1;
+    code = code * 4 + c;
+  }
+  return code;
+}
+
+/* Number of possible tokens = length of one bit vector (Section 6.1: 4^q). */
+uint64_t oracle_vector_bits(uint32_t q) {
+  uint64_t r = 1;
+  for (uint32_t j = 0; j < q; ++j) r *= 4;
+  return r;
+}
+
+/* Number of bins covering a reference of G bases with bins of B bases. */
+uint64_t oracle_num_bins(uint64_t G, uint32_t B) {
+  if (B == 0) return 0;
+  return (G + B - 1) / B;
+}
+
+/* Bytes of all bit vectors: one bit per token per bin (Section 6.1 footprint). */
+uint64_t oracle_index_bytes(uint64_t n_bins, uint32_t q) {
+  return n_bins * oracle_vector_bits(q) / 8;
+}
+
+/* Token starts that belong to bin x: [*lo, *hi). */
+void oracle_bin_extent(uint64_t x, uint64_t G, uint32_t B, uint32_t O, uint32_t q,
+                       uint64_t* lo, uint64_t* hi) {
+  uint64_t last_start_plus_one = (G >= q) ? G - q + 1 : 0;
+  uint64_t a = x * (uint64_t)B;
+  uint64_t b = a + (uint64_t)B + (uint64_t)O;
+  if (b > last_start_plus_one) b = last_start_plus_one;
+  if (a > b) a = b;
+  *lo = a;
+  *hi = b;
+}
+
+/* Bit vectors, one byte per existence bit: bits[x * 4^q + t] is 1 when token t
+ * starts inside bin x's extent (Section 3, bit vector generation). */
+int oracle_build_bits(const uint8_t* ref, uint64_t G, uint32_t B, uint32_t O, uint32_t q,
+                      uint8_t* bits, int nthreads) {
+  if (B == 0 || q == 0 || q > 12) return -1;
+  const uint64_t nb = oracle_num_bins(G, B);
+  const uint64_t R = oracle_vector_bits(q);
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t x = 0; x < (int64_t)nb; ++x) {
+    uint8_t* v = bits + (uint64_t)x * R;
+    memset(v, 0, R);
+    uint64_t lo, hi;
+    oracle_bin_extent((uint64_t)x, G, B, O, q, &lo, &hi);
+    for (uint64_t s = lo; s < hi; ++s) {
+      int64_t t = oracle_token_code(ref + s, q);
+      if (t >= 0) v[t] = 1;
+    }
+  }
+  return 0;
+}
+
+/* E from an error rate in per mille: ceil(e * L / 1000) (Section 6, caption of
+ * the read-existence figure). */
+uint32_t oracle_max_edits(uint32_t L, uint32_t e_permille) {
+  return (uint32_t)(((uint64_t)L * e_permille + 999) / 1000);
+}
+
+/* Threshold (Section 3): tokens of an exact match minus q per error. */
+int64_t oracle_threshold(uint32_t L, uint32_t q, uint32_t E) {
+  return ((int64_t)L - (int64_t)q + 1) - (int64_t)q * (int64_t)E;
+}
+
+/* Sum of the existence bits of every token of one read in one bin (steps 1-2). */
+uint32_t oracle_count(const uint8_t* bits_of_bin, const uint8_t* read, uint32_t L, uint32_t q) {
+  uint32_t count = 0;
+  for (uint32_t i = 0; i + q <= L; ++i) {
+    int64_t t = oracle_token_code(read + i, q);
+    if (t >= 0 && bits_of_bin[t]) count += 1;
+  }
+  return count;
+}
+
+static int64_t read_threshold(const int64_t* offsets, uint64_t r, uint32_t q,
+                              const uint16_t* max_edits, const uint16_t* err_pm_per_read,
+                              uint32_t err_permille) {
+  uint32_t L = (uint32_t)(offsets[r + 1] - offsets[r]);
+  uint32_t E;
+  if (max_edits) E = max_edits[r];
+  else if (err_pm_per_read) E = oracle_max_edits(L, err_pm_per_read[r]);
+  else E = oracle_max_edits(L, err_permille);
+  return oracle_threshold(L, q, E);
+}
+
+/* Threshold of every read, for checking the GPU's per-read threshold table. */
+void oracle_thresholds(const int64_t* offsets, uint64_t n, uint32_t q, const uint16_t* max_edits,
+                       const uint16_t* err_pm_per_read, uint32_t err_permille, int64_t* T_out) {
+  for (uint64_t r = 0; r < n; ++r)
+    T_out[r] = read_threshold(offsets, r, q, max_edits, err_pm_per_read, err_permille);
+}
+
+/* All-bins filter (Section 3 steps 1-3 for every bin): counts[r * nb + x] and
+ * pass[r * nb + x] = (count >= T_r). Either output may be NULL. */
+int oracle_scan_all(const uint8_t* bits, uint64_t nb, uint32_t q, const uint8_t* bases,
+                    const int64_t* offsets, uint64_t n, const uint16_t* max_edits,
+                    const uint16_t* err_pm_per_read, uint32_t err_permille,
+                    uint16_t* counts, uint8_t* pass, int nthreads) {
+  const uint64_t R = oracle_vector_bits(q);
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  const int64_t cells = (int64_t)(n * nb);
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t c = 0; c < cells; ++c) {
+    uint64_t r = (uint64_t)c / nb, x = (uint64_t)c % nb;
+    uint32_t L = (uint32_t)(offsets[r + 1] - offsets[r]);
+    uint32_t cnt = oracle_count(bits + x * R, bases + offsets[r], L, q);
+    int64_t T = read_threshold(offsets, r, q, max_edits, err_pm_per_read, err_permille);
+    if (counts) counts[c] = (uint16_t)cnt;
+    if (pass) pass[c] = (int64_t)cnt >= T ? 1 : 0;
+  }
+  return 0;
+}
+
+/* Candidate mode (Section 3 steps 4-5): read r's candidate bins are
+ * cand_bin[cand_off[r] .. cand_off[r+1]); outputs are in the same order. */
+int oracle_scan_candidates(const uint8_t* bits, uint64_t nb, uint32_t q, const uint8_t* bases,
+                           const int64_t* offsets, uint64_t n, const uint16_t* max_edits,
+                           const uint16_t* err_pm_per_read, uint32_t err_permille,
+                           const int64_t* cand_off, const int32_t* cand_bin,
+                           uint16_t* counts, uint8_t* pass, int nthreads) {
+  const uint64_t R = oracle_vector_bits(q);
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : bad)
+  for (int64_t r = 0; r < (int64_t)n; ++r) {
+    uint32_t L = (uint32_t)(offsets[r + 1] - offsets[r]);
+    int64_t T = read_threshold(offsets, (uint64_t)r, q, max_edits, err_pm_per_read, err_permille);
+    for (int64_t k = cand_off[r]; k < cand_off[r + 1]; ++k) {
+      int32_t x = cand_bin[k];
+      if (x < 0 || (uint64_t)x >= nb) { bad = 1; continue; }
+      uint32_t cnt = oracle_count(bits + (uint64_t)x * R, bases + offsets[r], L, q);
+      if (counts) counts[k] = (uint16_t)cnt;
+      if (pass) pass[k] = (int64_t)cnt >= T ? 1 : 0;
+    }
+  }
+  return bad ? -1 : 0;
+}
+
+/* Threads the parallel loops will use. */
+int oracle_threads(int nthreads) {
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  return omp_get_max_threads();
+}

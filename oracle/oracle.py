@@ -1,0 +1,186 @@
+"""ctypes front end of the GRIM-Filter CPU oracle (``grim_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the library and its binding never import this
+module. Only the tests, the smoke check and the benchmark's CPU-baseline leg
+use it, to check the GPU path and to time a CPU baseline.
+
+Every function mirrors one C function and cites the paper passage it
+follows (arXiv 1708.04329):
+  * bits               Section 3, bit vector generation; Section 6.1 (4^q bits)
+  * threshold          Section 3, threshold paragraph (L-(q-1) tokens, q per error)
+  * max_edits          Section 6, read-existence figure caption (ceil of L*e)
+  * scan_all           Section 3, steps 1-3 over every bin
+  * scan_candidates    Section 3, steps 4-5 (bin of the location's first base)
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "grim_oracle.c")
+_LIB = os.path.join(_HERE, "libgrimoracle.so")
+
+BUILD_CMD = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-Wall", "-Wextra"]
+
+
+def build(src: str = _SRC, out: str = _LIB) -> str:
+    subprocess.check_call(BUILD_CMD + [src, "-o", out + ".tmp"])
+    os.replace(out + ".tmp", out)
+    return out
+
+
+_cache = {}
+
+
+def load(path: str = _LIB):
+    """Load (building if absent) the oracle library at ``path``."""
+    if path in _cache:
+        return _cache[path]
+    if not os.path.exists(path):
+        if path != _LIB:
+            raise FileNotFoundError(path)
+        build()
+    lib = ctypes.CDLL(path)
+    P, U64, U32, I64, I = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int
+    lib.oracle_token_code.argtypes = [P, U32]
+    lib.oracle_token_code.restype = I64
+    lib.oracle_vector_bits.argtypes = [U32]
+    lib.oracle_vector_bits.restype = U64
+    lib.oracle_num_bins.argtypes = [U64, U32]
+    lib.oracle_num_bins.restype = U64
+    lib.oracle_index_bytes.argtypes = [U64, U32]
+    lib.oracle_index_bytes.restype = U64
+    lib.oracle_bin_extent.argtypes = [U64, U64, U32, U32, U32, P, P]
+    lib.oracle_bin_extent.restype = None
+    lib.oracle_build_bits.argtypes = [P, U64, U32, U32, U32, P, I]
+    lib.oracle_build_bits.restype = I
+    lib.oracle_max_edits.argtypes = [U32, U32]
+    lib.oracle_max_edits.restype = U32
+    lib.oracle_threshold.argtypes = [U32, U32, U32]
+    lib.oracle_threshold.restype = I64
+    lib.oracle_count.argtypes = [P, P, U32, U32]
+    lib.oracle_count.restype = U32
+    lib.oracle_thresholds.argtypes = [P, U64, U32, P, P, U32, P]
+    lib.oracle_thresholds.restype = None
+    lib.oracle_scan_all.argtypes = [P, U64, U32, P, P, U64, P, P, U32, P, P, I]
+    lib.oracle_scan_all.restype = I
+    lib.oracle_scan_candidates.argtypes = [P, U64, U32, P, P, U64, P, P, U32, P, P, P, P, I]
+    lib.oracle_scan_candidates.restype = I
+    lib.oracle_threads.argtypes = [I]
+    lib.oracle_threads.restype = I
+    _cache[path] = lib
+    return lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _u8(a) -> np.ndarray:
+    if isinstance(a, (bytes, bytearray)):
+        return np.frombuffer(bytes(a), dtype=np.uint8)
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+class Oracle:
+    """Plain-loop GRIM-Filter on the CPU (one byte per existence bit)."""
+
+    def __init__(self, path: str = _LIB, threads: int = 0):
+        self.lib = load(path)
+        self.threads = threads
+
+    # -- small helpers, one per paper formula ---------------------------------
+    def token_code(self, s: bytes, q: int) -> int:
+        return int(self.lib.oracle_token_code(_p(_u8(s)), q))
+
+    def vector_bits(self, q: int) -> int:
+        return int(self.lib.oracle_vector_bits(q))
+
+    def num_bins(self, G: int, B: int) -> int:
+        return int(self.lib.oracle_num_bins(G, B))
+
+    def index_bytes(self, n_bins: int, q: int) -> int:
+        return int(self.lib.oracle_index_bytes(n_bins, q))
+
+    def bin_extent(self, x: int, G: int, B: int, O: int, q: int):
+        lo, hi = ctypes.c_uint64(), ctypes.c_uint64()
+        self.lib.oracle_bin_extent(x, G, B, O, q, ctypes.byref(lo), ctypes.byref(hi))
+        return lo.value, hi.value
+
+    def max_edits(self, L: int, e_permille: int) -> int:
+        return int(self.lib.oracle_max_edits(L, e_permille))
+
+    def threshold(self, L: int, q: int, E: int) -> int:
+        return int(self.lib.oracle_threshold(L, q, E))
+
+    # -- bit vectors and scans -----------------------------------------------
+    def bits(self, ref, B: int, O: int, q: int) -> np.ndarray:
+        """uint8 [n_bins, 4^q]: 1 where the token starts inside the bin's extent."""
+        ref = _u8(ref)
+        nb = self.num_bins(len(ref), B)
+        out = np.empty((nb, self.vector_bits(q)), dtype=np.uint8)
+        if self.lib.oracle_build_bits(_p(ref), len(ref), B, O, q, _p(out), self.threads) != 0:
+            raise ValueError("oracle_build_bits: bad parameters")
+        return out
+
+    def count(self, bits_of_bin: np.ndarray, read: bytes, q: int) -> int:
+        rd = _u8(read)
+        return int(self.lib.oracle_count(_p(np.ascontiguousarray(bits_of_bin, np.uint8)), _p(rd), len(rd), q))
+
+    @staticmethod
+    def _edits(n, max_edits, err_pm_per_read):
+        me = None if max_edits is None else np.ascontiguousarray(max_edits, np.uint16)
+        ep = None if err_pm_per_read is None else np.ascontiguousarray(err_pm_per_read, np.uint16)
+        for a in (me, ep):
+            if a is not None and len(a) != n:
+                raise ValueError("per-read array length")
+        return me, ep
+
+    def thresholds(self, offsets, q, max_edits=None, err_pm_per_read=None, err_permille=0):
+        offs = np.ascontiguousarray(offsets, np.int64)
+        n = len(offs) - 1
+        me, ep = self._edits(n, max_edits, err_pm_per_read)
+        out = np.empty(n, dtype=np.int64)
+        self.lib.oracle_thresholds(_p(offs), n, q, _p(me), _p(ep), err_permille, _p(out))
+        return out
+
+    def scan_all(self, bits: np.ndarray, q: int, bases, offsets, max_edits=None,
+                 err_pm_per_read=None, err_permille: int = 0, want_counts: bool = True):
+        """(counts uint16 [n, nb] or None, pass uint8 [n, nb])."""
+        bases = _u8(bases)
+        offs = np.ascontiguousarray(offsets, np.int64)
+        n, nb = len(offs) - 1, bits.shape[0]
+        me, ep = self._edits(n, max_edits, err_pm_per_read)
+        counts = np.empty((n, nb), dtype=np.uint16) if want_counts else None
+        pas = np.empty((n, nb), dtype=np.uint8)
+        self.lib.oracle_scan_all(_p(bits), nb, q, _p(bases), _p(offs), n, _p(me), _p(ep),
+                                 err_permille, _p(counts), _p(pas), self.threads)
+        return counts, pas
+
+    def scan_candidates(self, bits: np.ndarray, q: int, bases, offsets, cand_off, cand_bin,
+                        max_edits=None, err_pm_per_read=None, err_permille: int = 0):
+        """(counts uint16 [P], pass uint8 [P]) in candidate (CSR) order."""
+        bases = _u8(bases)
+        offs = np.ascontiguousarray(offsets, np.int64)
+        co = np.ascontiguousarray(cand_off, np.int64)
+        cb = np.ascontiguousarray(cand_bin, np.int32)
+        n, nb = len(offs) - 1, bits.shape[0]
+        me, ep = self._edits(n, max_edits, err_pm_per_read)
+        P = len(cb)
+        counts = np.empty(P, dtype=np.uint16)
+        pas = np.empty(P, dtype=np.uint8)
+        rc = self.lib.oracle_scan_candidates(_p(bits), nb, q, _p(bases), _p(offs), n, _p(me), _p(ep),
+                                             err_permille, _p(co), _p(cb), _p(counts), _p(pas),
+                                             self.threads)
+        if rc != 0:
+            raise ValueError("candidate bin out of range")
+        return counts, pas
+
+    def threads_used(self) -> int:
+        return int(self.lib.oracle_threads(self.threads))

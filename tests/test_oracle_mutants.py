@@ -1,0 +1,79 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case copies the oracle source, plants one mistake by text substitution,
+builds it on the CPU, and runs the pin functions against it: at least one pin
+must fail. The oracle source itself is never modified.
+"""
+
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import tempfile
+
+import pytest
+
+import test_oracle_pins as pins
+from oracle import Oracle
+from oracle.oracle import BUILD_CMD, _SRC
+
+MUTANTS = {
+    "threshold_q_minus_1_per_error": ("(int64_t)q * (int64_t)E", "((int64_t)q - 1) * (int64_t)E"),
+    "threshold_token_count_off_by_one": ("((int64_t)L - (int64_t)q + 1)", "((int64_t)L - (int64_t)q)"),
+    "no_bin_overlap": ("a + (uint64_t)B + (uint64_t)O", "a + (uint64_t)B"),
+    "strict_comparison_pass": ("(int64_t)cnt >= T ? 1 : 0;\n  }\n  return 0;", "(int64_t)cnt > T ? 1 : 0;\n  }\n  return 0;"),
+    "floor_error_budget": ("e_permille + 999) / 1000", "e_permille) / 1000"),
+    "last_read_token_dropped": ("i + q <= L", "i + q < L"),
+    "colliding_token_code": ("code = code * 4 + c;", "code = code * 3 + c;"),
+    "n_read_as_a": ("if (c < 0) return -1;\n    code", "if (c < 0) c = 0;\n    code"),
+    "last_reference_window_dropped": ("? G - q + 1 : 0", "? G - q : 0"),
+    "partial_last_bin_dropped": ("return (G + B - 1) / B;", "return G / B;"),
+    "bins_not_extended_at_start": ("uint64_t a = x * (uint64_t)B;", "uint64_t a = x * (uint64_t)B + 1;"),
+}
+
+PIN_CALLS = [
+    lambda o: pins.test_vector_length_q5(o),
+    lambda o: pins.test_index_footprint_paper(o),
+    lambda o: pins.test_counter_width_100bp(o),
+    lambda o: pins.test_exact_match_threshold(o),
+    lambda o: pins.test_ceil_error_budget(o),
+    lambda o: pins.test_error_propagation_q4(o),
+    *[(lambda o, a=a: pins.test_threshold_is_tight(o, *a)) for a in [(3, 30, 2), (4, 40, 3), (5, 60, 4)]],
+    *[(lambda o, s=s: pins.test_counts_match_set_recount(o, s)) for s in range(6)],
+    lambda o: pins.test_bits_match_set_definition(o),
+    *[(lambda o, s=s: pins.test_no_false_negatives_bruteforce(o, s)) for s in range(2)],
+    lambda o: pins.test_exact_substring_counts_all_tokens(o),
+    lambda o: pins.test_homopolymer(o),
+    lambda o: pins.test_first_base_rule(o),
+    lambda o: pins.test_last_partial_bin_and_tail_token(o),
+    lambda o: pins.test_n_windows(o),
+    lambda o: pins.test_nonpositive_threshold_passes_everything(o),
+]
+
+
+def _build_mutant(tmp: str, old: str, new: str) -> str:
+    src = open(_SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not unique: {old!r}"
+    path = os.path.join(tmp, "mutant.c")
+    open(path, "w").write(src.replace(old, new))
+    out = os.path.join(tmp, "libmutant.so")
+    subprocess.check_call(BUILD_CMD + [path, "-o", out])
+    return out
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name):
+    old, new = MUTANTS[name]
+    tmp = tempfile.mkdtemp(prefix="oracle_mutant_")
+    try:
+        mutant = Oracle(_build_mutant(tmp, old, new))
+        caught = 0
+        for call in PIN_CALLS:
+            try:
+                call(mutant)
+            except (AssertionError, ValueError, IndexError):
+                caught += 1
+        assert caught > 0, f"no pin catches mutant {name}"
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
