@@ -1,0 +1,199 @@
+/*
+ * grim.h - C ABI of the GRIM-Filter hot path on AMD Instinct MI355X (gfx950).
+ *
+ * GRIM-Filter (Kim et al., arXiv 1708.04329) rejects read-mapping locations
+ * before alignment. The reference genome is cut into overlapping bins; each
+ * bin keeps one existence bit per possible token (q-gram); a read passes a bin
+ * when the number of its tokens present there reaches a threshold that no
+ * location within E edits can miss.
+ *
+ * Conventions for every entry point:
+ *   - Return value 0 (GRIM_OK) or a negative GRIM_E* code. No exception or
+ *     abort crosses this boundary. grim_last_error() gives a message for the
+ *     last failure on the calling thread.
+ *   - The caller owns every input and output buffer. The library owns
+ *     grim_index handles and frees them in grim_index_free.
+ *   - "device" buffers are HIP device memory on the device that holds the
+ *     index; "host" buffers are ordinary process memory.
+ *   - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on that stream; every call below returns after its
+ *     work on the stream is complete, so outputs are ready on return.
+ *   - Bases are ASCII bytes; A, C, G, T are accepted in either case; any
+ *     other byte (N, ...) makes every token window that holds it invalid.
+ */
+#ifndef GRIM_H
+#define GRIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRIM_ABI_VERSION 1
+
+enum grim_status {
+  GRIM_OK = 0,
+  GRIM_EINVAL = -1,     /* an argument or an input value is out of range */
+  GRIM_ENOMEM = -2,     /* a device or host allocation failed */
+  GRIM_EDEVICE = -3,    /* HIP runtime failure, or no gfx950 device */
+  GRIM_EOVERLAP = -4,   /* a read is not covered by the bin overlap: O < L + E - q */
+  GRIM_EAGAIN = -5,     /* result not ready yet */
+  GRIM_ETIMEDOUT = -6,  /* a wait ran out of time */
+  GRIM_ECANCELED = -7,  /* work was cancelled */
+  GRIM_EIO = -8         /* index file unreadable, truncated or corrupt */
+};
+
+/* Index layouts (bit flags; one index may hold both). */
+#define GRIM_LAYOUT_TM 1u /* token-major: row t = bit x of every bin x (all-bins scan) */
+#define GRIM_LAYOUT_BM 2u /* bin-major: bin x = its 4^q-bit vector (candidate checks) */
+
+/* grim_reads.flags */
+#define GRIM_READS_ALLOW_SHORT_OVERLAP 1u /* compute reads with O < L + E - q instead of
+                                             failing with GRIM_EOVERLAP; their result is
+                                             still the defined count, but a location within
+                                             E edits may then be rejected */
+
+typedef struct grim_index grim_index;
+
+typedef struct {
+  uint64_t ref_len;      /* G: reference length in bases */
+  uint32_t bin_size;     /* B: bases per bin */
+  uint32_t overlap;      /* O: bases each bin extends into the next */
+  uint32_t q;            /* token length */
+  uint32_t layout;       /* GRIM_LAYOUT_* flags present */
+  uint64_t n_bins;       /* ceil(G / B) */
+  uint64_t mask_words;   /* W = ceil(n_bins / 32): uint32 words per read in a pass mask */
+  uint64_t tm_row_words; /* uint32 words per token-major row (>= W, zero padded) */
+  uint32_t bm_vec_words; /* uint32 words per bin-major vector = max(1, 4^q / 32) */
+  int32_t device;        /* HIP device ordinal that holds the index */
+  uint64_t tm_bytes;     /* device bytes of the token-major layout (0 if absent) */
+  uint64_t bm_bytes;     /* device bytes of the bin-major layout (0 if absent) */
+  uint64_t bits_bytes;   /* n_bins * 4^q / 8: the existence bits themselves */
+} grim_index_info_t;
+
+/* A read set. Read r is bases[offsets[r] .. offsets[r+1]) and has length L_r.
+ * Its error budget is E_r = max_edits[r] if max_edits is given, else
+ * ceil(err_permille[r] * L_r / 1000) if err_permille is given, else
+ * ceil(err_permille_all * L_r / 1000) (paper Section 6, read-existence figure
+ * caption: the ceiling of read length times error tolerance). Its threshold
+ * is T_r = (L_r - q + 1) - q * E_r (Section 3: an exact match keeps all
+ * L - (q - 1) tokens and each error can destroy q of them). */
+typedef struct {
+  const uint8_t* bases;          /* [n_bases] ASCII bases of all reads, concatenated */
+  const int64_t* offsets;        /* [n_reads + 1], non-decreasing, within [0, n_bases] */
+  uint64_t n_reads;
+  uint64_t n_bases;
+  const uint16_t* max_edits;     /* [n_reads] explicit E_r, or NULL */
+  const uint16_t* err_permille;  /* [n_reads] per-read error rate in per mille, or NULL */
+  uint32_t err_permille_all;     /* error rate for every read when both arrays are NULL */
+  uint32_t on_device;            /* 1: bases, offsets, max_edits, err_permille are device
+                                    pointers; 0: host pointers (copied in by the call) */
+  uint32_t flags;                /* GRIM_READS_* */
+  uint32_t reserved;
+} grim_reads;
+
+/* ABI version of the loaded library (GRIM_ABI_VERSION it was built with). */
+int grim_abi_version(void);
+
+/* Message for the last failed call on this thread ("" if none). The pointer
+ * stays valid until the next call on this thread. */
+const char* grim_last_error(void);
+
+/* Build the bit vectors of a reference (Section 3, bit vector generation):
+ * bin x = [x*B, x*B + B) extended by O bases; bit t of bin x is set when a
+ * valid token with code t starts at some s with x*B <= s < x*B + B + O and
+ * s <= G - q (a token belongs to the bin holding its first base). Token code:
+ * A=0, C=1, G=2, T=3, first base most significant. The bits are stored in the
+ * layouts `layout` asks for (GRIM_LAYOUT_TM and/or GRIM_LAYOUT_BM).
+ *   ref, ref_len   reference bases (host, or device if ref_on_device = 1)
+ *   bin_size       B >= 1; overlap O >= 0; q in [1, 7]
+ *   out            receives a new handle, resident on the current HIP device
+ * Errors: GRIM_EINVAL (bad sizes, ref_len < q, more than 2^31 bins),
+ *         GRIM_ENOMEM, GRIM_EDEVICE. */
+int grim_build_index(const uint8_t* ref, uint64_t ref_len, uint32_t ref_on_device,
+                     uint32_t bin_size, uint32_t overlap, uint32_t q, uint32_t layout,
+                     void* hip_stream, grim_index** out);
+
+/* Describe an index (sizes and layout). */
+int grim_index_info(const grim_index* idx, grim_index_info_t* out);
+
+/* Copy `nbytes` of one stored layout, starting at byte `offset`, to host
+ * memory `dst` (for inspection and tests). Token-major bytes are row t of
+ * tm_row_words uint32 words, bit (x % 32) of word x / 32 = bin x; bin-major
+ * bytes are bin x of bm_vec_words words, bit (t % 32) of word t / 32 = token t.
+ * Errors: GRIM_EINVAL (layout absent, range outside it). */
+int grim_index_read(const grim_index* idx, uint32_t layout, uint64_t offset, uint64_t nbytes,
+                    void* dst);
+
+/* Save the bit vectors for later reuse (Section 3: the bit vectors are built
+ * once per reference and saved). The file holds a versioned header with the
+ * parameters and a checksum. Errors: GRIM_EIO. */
+int grim_index_save(const grim_index* idx, const char* path);
+
+/* Load an index saved by grim_index_save onto the current HIP device.
+ * Errors: GRIM_EIO (missing, truncated, bad magic/version/checksum),
+ *         GRIM_ENOMEM, GRIM_EDEVICE. */
+int grim_index_load(const char* path, void* hip_stream, grim_index** out);
+
+/* Free an index and its device memory (NULL is ignored). */
+void grim_index_free(grim_index* idx);
+
+/* All-bins filter (Section 3 steps 1-3 for every bin; Section 4.2: one pass
+ * bit per bin per read). For read r and bin x:
+ *   count[r][x] = number of token positions i in [0, L_r - q] whose window
+ *                 read[i .. i+q) is valid and has its bit set in bin x
+ *                 (repeated tokens count every time);
+ *   pass[r][x]  = count[r][x] >= T_r.
+ * Needs GRIM_LAYOUT_TM.
+ *   mask_out    device, [n_reads][mask_words] uint32: bit (x % 32) of word x/32
+ *               is pass[r][x]; bits at x >= n_bins are 0.
+ *   counts_out  device, NULL or [n_reads][n_bins] counts of counts_bytes each
+ *               (1: uint8, every read must have L - q + 1 <= 255; 2: uint16).
+ * Errors: GRIM_EINVAL (layout missing, L_r < q, bad offsets, counts_bytes),
+ *         GRIM_EOVERLAP (see GRIM_READS_ALLOW_SHORT_OVERLAP). On error the
+ *         outputs are left unwritten. */
+int grim_filter_scan(const grim_index* idx, const grim_reads* reads, uint32_t* mask_out,
+                     void* counts_out, uint32_t counts_bytes, void* hip_stream);
+
+/* Candidate-location filter (Section 3 steps 4-5: a location is checked
+ * against the bin holding its first base). Read r's candidate bins are
+ * cand_bin[cand_off[r] .. cand_off[r+1]); for each entry k the call writes
+ *   count_out[k] = count[r][cand_bin[k]] and pass_out[k] = count >= T_r.
+ * Needs GRIM_LAYOUT_BM.
+ *   cand_off    device, [n_reads + 1] int64, non-decreasing, cand_off[0] = 0
+ *   cand_bin    device, [n_cand] int32, each in [0, n_bins)
+ *   count_out   device, [n_cand] uint16, or NULL
+ *   pass_out    device, [n_cand] uint8 (0/1), or NULL
+ * Errors: GRIM_EINVAL (layout missing, bin out of range, bad offsets),
+ *         GRIM_EOVERLAP. On error the outputs are unspecified. */
+int grim_filter_candidates(const grim_index* idx, const grim_reads* reads,
+                           const int64_t* cand_off, const int32_t* cand_bin, uint64_t n_cand,
+                           uint16_t* count_out, uint8_t* pass_out, void* hip_stream);
+
+/* Kernel timing, recorded with HIP events on the stream each kernel runs on. */
+typedef struct {
+  uint64_t launches;
+  double total_ms;
+  double last_ms;
+} grim_kernel_time;
+
+typedef struct {
+  grim_kernel_time tokenize;    /* read tokenisation + thresholds */
+  grim_kernel_time scan;        /* all-bins accumulate + threshold */
+  grim_kernel_time candidates;  /* candidate checks */
+  grim_kernel_time build;       /* index build */
+} grim_profile_t;
+
+/* Turn event timing of library kernels on (1) or off (0). */
+int grim_profile_enable(int on);
+
+/* Read the accumulated timings; reset them if `reset` is non-zero. */
+int grim_profile_read(grim_profile_t* out, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRIM_H */

@@ -1,0 +1,180 @@
+// Internal declarations shared by the HIP translation units of libgrim.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+
+#include "grim.h"
+
+namespace grim {
+
+// ---------------------------------------------------------------------------
+// Error reporting: every entry point returns a code and leaves a message.
+// ---------------------------------------------------------------------------
+int set_error(int code, const char* fmt, ...);
+const char* last_error();
+void clear_error();
+
+#define GRIM_HIP_TRY(expr)                                                          \
+  do {                                                                              \
+    hipError_t _e = (expr);                                                         \
+    if (_e != hipSuccess)                                                           \
+      return ::grim::set_error(_e == hipErrorOutOfMemory ? GRIM_ENOMEM : GRIM_EDEVICE, \
+                               "%s failed: %s", #expr, hipGetErrorString(_e));      \
+  } while (0)
+
+// Device status words written by kernels (status[0] holds error bits).
+enum : uint32_t {
+  ST_BAD_LENGTH = 1u,      // L < q or offsets out of order / out of range
+  ST_OVERLAP = 2u,         // O < L + E - q without GRIM_READS_ALLOW_SHORT_OVERLAP
+  ST_COUNT_U8 = 4u,        // uint8 counts asked for a read with more than 255 tokens
+  ST_TOO_LONG = 8u,        // more than 65535 tokens in a read
+  ST_BAD_BIN = 16u,        // candidate bin outside [0, n_bins)
+  ST_BAD_CAND_OFF = 32u,   // candidate offsets out of order / out of range
+};
+int status_to_error(uint32_t st);
+
+// Token storage: read r's tokens start at token_base(offsets[r], r) (a multiple
+// of 32 tokens) and are padded with the code R4 = 4^q up to a multiple of 32.
+// The regions of consecutive reads never overlap, and the buffer needs
+// token_capacity(n_bases, n_reads) entries.
+__host__ __device__ inline uint64_t token_base(int64_t off, uint64_t r) {
+  return ((uint64_t)off + 64ull * r + 31ull) & ~31ull;
+}
+inline uint64_t token_capacity(uint64_t n_bases, uint64_t n_reads) {
+  return n_bases + 64ull * (n_reads + 1) + 64ull;
+}
+
+// Tile width in uint32 words of the token-major layout, by q: the tile of
+// (4^q + 1) rows must fit the 160 KB of LDS of one CU.
+inline int tm_tile_words(uint32_t q) { return q <= 5 ? 32 : (q == 6 ? 8 : 2); }
+constexpr uint64_t kTmRowAlign = 64;  // token-major rows padded to 64 words
+
+// ---------------------------------------------------------------------------
+// Kernel argument blocks and launchers (one translation unit each).
+// ---------------------------------------------------------------------------
+struct TokArgs {
+  const uint8_t* bases;
+  const int64_t* offsets;
+  uint64_t n_reads;
+  uint64_t n_bases;
+  const uint16_t* max_edits;
+  const uint16_t* err_pm;
+  uint32_t err_pm_all;
+  uint32_t q;
+  uint32_t overlap;
+  uint32_t flags;
+  uint32_t max_tokens;  // 255 when uint8 counts are requested, else 65535
+  uint16_t* tokens;
+  int32_t* thr;
+  uint32_t* status;
+};
+hipError_t launch_tokenize(const TokArgs& a, hipStream_t s);
+
+struct BuildArgs {
+  const uint8_t* ref;
+  uint64_t G;
+  uint32_t B, O, q;
+  uint64_t nb;
+  uint32_t* tm;          // token-major output or null
+  uint64_t row_words;
+  uint32_t* bm;          // bin-major output or null
+  uint32_t vec_words;
+};
+hipError_t launch_build_tm(const BuildArgs& a, hipStream_t s);
+hipError_t launch_build_bm(const BuildArgs& a, hipStream_t s);
+
+struct ScanArgs {
+  const uint32_t* tm;
+  uint64_t row_words;
+  uint32_t R4;
+  uint32_t q;
+  uint64_t nb;
+  uint64_t W;
+  const uint16_t* tokens;
+  const int64_t* offsets;
+  const int32_t* thr;
+  const uint32_t* read_order;  // chunk position -> read index, or null for identity
+  uint64_t n_reads;
+  uint32_t reads_per_chunk;
+  uint32_t n_tiles;
+  uint32_t n_rchunks;
+  uint32_t* mask_out;
+  void* counts_out;
+  uint32_t counts_bytes;
+  const uint32_t* status;
+};
+struct ScanConfig {
+  int threads = 512;          // threads per workgroup
+  int reads_per_chunk = 4096; // reads per workgroup
+};
+hipError_t launch_scan_allbins(const ScanArgs& a, const ScanConfig& cfg, hipStream_t s);
+
+struct CandArgs {
+  const uint32_t* bm;
+  uint32_t vec_words;
+  uint32_t R4;
+  uint32_t q;
+  uint64_t nb;
+  const uint16_t* tokens;
+  const int64_t* offsets;
+  const int32_t* thr;
+  uint64_t n_reads;
+  const int64_t* cand_off;
+  const int32_t* cand_bin;
+  uint64_t n_cand;
+  uint16_t* count_out;
+  uint8_t* pass_out;
+  uint32_t* status;
+};
+hipError_t launch_scan_candidates(const CandArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Profiling: HIP events around kernels, on the stream they run on.
+// ---------------------------------------------------------------------------
+enum ProfKind { PROF_TOKENIZE = 0, PROF_SCAN = 1, PROF_CAND = 2, PROF_BUILD = 3, PROF_N = 4 };
+bool profiling();
+struct ProfSpan {
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ProfKind kind;
+  bool on = false;
+  explicit ProfSpan(ProfKind k) : kind(k) {}
+  ProfSpan(const ProfSpan&) = delete;
+  ProfSpan& operator=(const ProfSpan&) = delete;
+  void start(hipStream_t s);
+  void stop(hipStream_t s);
+  void collect();  // after the stream is synchronised
+  ~ProfSpan();
+};
+
+}  // namespace grim
+
+// ---------------------------------------------------------------------------
+// The index handle.
+// ---------------------------------------------------------------------------
+struct grim_workspace {
+  uint16_t* tokens = nullptr;
+  uint64_t tokens_cap = 0;
+  int32_t* thr = nullptr;
+  uint64_t thr_cap = 0;
+  uint32_t* status = nullptr;      // device [8]
+  uint32_t* status_host = nullptr; // pinned [8]
+  uint8_t* staging = nullptr;      // device copies of host-resident inputs
+  uint64_t staging_cap = 0;
+};
+
+struct grim_index {
+  int device = 0;
+  uint64_t G = 0;
+  uint32_t B = 0, O = 0, q = 0, layout = 0;
+  uint64_t nb = 0, W = 0, row_words = 0;
+  uint32_t R4 = 0, vec_words = 0;
+  uint32_t* tm = nullptr;
+  uint32_t* bm = nullptr;
+  uint64_t tm_bytes = 0, bm_bytes = 0;
+  std::mutex mu;  // guards ws for the duration of a call
+  grim_workspace ws;
+};

@@ -1,0 +1,152 @@
+// Candidate-location filter (paper Section 3 steps 4-5): for each listed
+// (read, bin) pair, count the read's tokens present in that bin's bit vector
+// and compare with T_r.
+//
+// The count with multiplicity, sum_i bit[x][t_i], is rewritten as
+// sum_j 2^j * popcount(vec_x AND plane_j), where plane_j is the 4^q-bit set of
+// tokens whose number of occurrences in the read has bit j set. One
+// wavefront handles one read: it builds the read's token histogram and its
+// multiplicity planes in LDS once, then each lane takes one candidate bin,
+// streams that bin's vector (128 B at q=5, 512 B at q=6) from HBM with
+// 16-byte loads and ANDs it with the planes (read from LDS with a
+// wave-uniform address, i.e. a broadcast), counting with v_bcnt. The gather
+// of one bin vector per pair is the compulsory traffic of this mode.
+
+#include "grim_internal.h"
+
+namespace grim {
+namespace {
+
+constexpr int kMaxPlanes = 16;  // multiplicities up to 65535
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int VW, int NW>
+__global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
+  constexpr uint32_t kHistWords = VW * 16;          // R4 / 2 packed uint16 counters (R4 = 32*VW)
+  constexpr uint32_t kPerWave = kHistWords + kMaxPlanes * VW;
+  __shared__ __attribute__((aligned(16))) uint32_t lds[NW * kPerWave];
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  uint32_t* hist = lds + wave * kPerWave;
+  uint32_t* planes = hist + kHistWords;
+  const uint64_t r = (uint64_t)blockIdx.x * NW + wave;
+  if (r >= a.n_reads) return;
+  if (a.status[0] & ~(uint32_t)(ST_BAD_BIN | ST_BAD_CAND_OFF)) return;  // rejected reads
+  const int64_t c0 = a.cand_off[r], c1 = a.cand_off[r + 1];
+  if (c0 < 0 || c1 < c0 || (uint64_t)c1 > a.n_cand) {
+    if (lane == 0) atomicOr(a.status, ST_BAD_CAND_OFF);
+    return;
+  }
+  if (c0 == c1) return;
+  const int64_t o0 = a.offsets[r], o1 = a.offsets[r + 1];
+  const uint32_t ntok = (uint32_t)(o1 - o0 - a.q + 1);
+  const uint16_t* tok = a.tokens + token_base(o0, r);
+  const int32_t T = a.thr[r];
+  const uint32_t R4 = a.R4;
+
+  // 1. token histogram (uint16 counters packed in pairs)
+  for (uint32_t i = lane; i < kHistWords; i += 64) hist[i] = 0;
+  wave_sync();
+  for (uint32_t i = lane; i < ntok; i += 64) {
+    const uint32_t t = tok[i];
+    if (t < R4) atomicAdd(&hist[t >> 1], 1u << ((t & 1u) * 16));
+  }
+  wave_sync();
+  // 2. number of planes = bit length of the largest multiplicity
+  uint32_t mx = 0;
+  for (uint32_t i = lane; i < kHistWords; i += 64) {
+    const uint32_t h = hist[i];
+    mx = max(mx, max(h & 0xFFFFu, h >> 16));
+  }
+  for (int off = 32; off >= 1; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+  const uint32_t K = mx ? 32u - __clz(mx) : 0u;
+  // 3. planes: bit b of plane j word w = bit j of the count of token 32*w + b
+  for (uint32_t w = lane; w < VW; w += 64) {
+    uint32_t m2[16];  // counts of tokens 32w .. 32w+31, two per word
+#pragma unroll
+    for (int i = 0; i < 16; ++i) m2[i] = hist[w * 16 + i];
+    for (uint32_t j = 0; j < K; ++j) {
+      uint32_t pw = 0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        pw |= ((m2[i] >> j) & 1u) << (2 * i);
+        pw |= ((m2[i] >> (16 + j)) & 1u) << (2 * i + 1);
+      }
+      planes[j * VW + w] = pw;
+    }
+  }
+  wave_sync();
+  // 4. one candidate per lane
+  for (int64_t cb = c0; cb < c1; cb += 64) {
+    const int64_t c = cb + lane;
+    if (c >= c1) break;
+    const int32_t x = a.cand_bin[c];
+    uint32_t cnt = 0;
+    if (x < 0 || (uint64_t)x >= a.nb) {
+      atomicOr(a.status, ST_BAD_BIN);
+    } else {
+      const uint32_t* vec = a.bm + (uint64_t)x * VW;
+      uint32_t acc[4] = {0, 0, 0, 0};
+      if constexpr (VW >= 4) {
+        const uint4* v4 = reinterpret_cast<const uint4*>(vec);
+#pragma unroll 8
+        for (int w4 = 0; w4 < VW / 4; ++w4) {
+          const uint4 v = v4[w4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if ((uint32_t)j < K) {
+              const uint4 p = reinterpret_cast<const uint4*>(planes + j * VW)[w4];
+              acc[j] += __popc(v.x & p.x) + __popc(v.y & p.y) + __popc(v.z & p.z) + __popc(v.w & p.w);
+            }
+          }
+        }
+        for (uint32_t j = 4; j < K; ++j) {  // rare: a token repeated 16 times or more
+          uint32_t extra = 0;
+          for (int w4 = 0; w4 < VW / 4; ++w4) {
+            const uint4 v = v4[w4];
+            const uint4 p = reinterpret_cast<const uint4*>(planes + j * VW)[w4];
+            extra += __popc(v.x & p.x) + __popc(v.y & p.y) + __popc(v.z & p.z) + __popc(v.w & p.w);
+          }
+          cnt += extra << j;
+        }
+      } else {
+        for (int w = 0; w < VW; ++w) {
+          const uint32_t v = vec[w];
+          for (uint32_t j = 0; j < K; ++j) cnt += (uint32_t)__popc(v & planes[j * VW + w]) << j;
+        }
+      }
+      cnt += acc[0] + (acc[1] << 1) + (acc[2] << 2) + (acc[3] << 3);
+    }
+    if (a.count_out) a.count_out[c] = (uint16_t)cnt;
+    if (a.pass_out) a.pass_out[c] = (int32_t)cnt >= T ? 1 : 0;
+  }
+}
+
+template <int VW>
+hipError_t launch_vw(const CandArgs& a, hipStream_t s) {
+  constexpr int NW = VW >= 512 ? 1 : (VW >= 128 ? 4 : 8);
+  const uint64_t blocks = (a.n_reads + NW - 1) / NW;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_scan_cand<VW, NW>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_scan_candidates(const CandArgs& a, hipStream_t s) {
+  switch (a.vec_words) {
+    case 1: return launch_vw<1>(a, s);
+    case 2: return launch_vw<2>(a, s);
+    case 8: return launch_vw<8>(a, s);
+    case 32: return launch_vw<32>(a, s);
+    case 128: return launch_vw<128>(a, s);
+    case 512: return launch_vw<512>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace grim

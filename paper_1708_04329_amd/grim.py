@@ -1,0 +1,300 @@
+"""Python binding of libgrim (include/grim.h): argument marshalling only.
+
+Every step of the filter runs in the HIP library; this module turns torch
+tensors (device memory) or numpy arrays (host memory) into the plain pointers
+and sizes of the C ABI and raises ``GrimError`` for non-zero return codes.
+There is no fallback: if ``libgrim.so`` is missing or the device is not a
+gfx950 GPU, calls fail loudly.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgrim.so")
+
+GRIM_OK = 0
+GRIM_EINVAL = -1
+GRIM_ENOMEM = -2
+GRIM_EDEVICE = -3
+GRIM_EOVERLAP = -4
+GRIM_EAGAIN = -5
+GRIM_ETIMEDOUT = -6
+GRIM_ECANCELED = -7
+GRIM_EIO = -8
+
+LAYOUT_TM = 1
+LAYOUT_BM = 2
+READS_ALLOW_SHORT_OVERLAP = 1
+
+_NAMES = {0: "GRIM_OK", -1: "GRIM_EINVAL", -2: "GRIM_ENOMEM", -3: "GRIM_EDEVICE", -4: "GRIM_EOVERLAP",
+          -5: "GRIM_EAGAIN", -6: "GRIM_ETIMEDOUT", -7: "GRIM_ECANCELED", -8: "GRIM_EIO"}
+
+
+class GrimError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class IndexInfo(ctypes.Structure):
+    _fields_ = [("ref_len", ctypes.c_uint64), ("bin_size", ctypes.c_uint32), ("overlap", ctypes.c_uint32),
+                ("q", ctypes.c_uint32), ("layout", ctypes.c_uint32), ("n_bins", ctypes.c_uint64),
+                ("mask_words", ctypes.c_uint64), ("tm_row_words", ctypes.c_uint64),
+                ("bm_vec_words", ctypes.c_uint32), ("device", ctypes.c_int32), ("tm_bytes", ctypes.c_uint64),
+                ("bm_bytes", ctypes.c_uint64), ("bits_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class _Reads(ctypes.Structure):
+    _fields_ = [("bases", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("n_reads", ctypes.c_uint64),
+                ("n_bases", ctypes.c_uint64), ("max_edits", ctypes.c_void_p), ("err_permille", ctypes.c_void_p),
+                ("err_permille_all", ctypes.c_uint32), ("on_device", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double), ("last_ms", ctypes.c_double)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("tokenize", KernelTime), ("scan", KernelTime), ("candidates", KernelTime), ("build", KernelTime)]
+
+
+EXPORTS = ["grim_abi_version", "grim_last_error", "grim_build_index", "grim_index_info", "grim_index_read",
+           "grim_index_save", "grim_index_load", "grim_index_free", "grim_filter_scan", "grim_filter_candidates",
+           "grim_profile_enable", "grim_profile_read"]
+
+_lib = None
+
+
+def lib(path: str = LIB_PATH):
+    """Load libgrim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with `python -m paper_1708_04329_amd.build`")
+    L = ctypes.CDLL(path)
+    P, U32, U64, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "grim_abi_version": ([], I),
+        "grim_last_error": ([], ctypes.c_char_p),
+        "grim_build_index": ([P, U64, U32, U32, U32, U32, U32, P, PP], I),
+        "grim_index_info": ([P, ctypes.POINTER(IndexInfo)], I),
+        "grim_index_read": ([P, U32, U64, U64, P], I),
+        "grim_index_save": ([P, ctypes.c_char_p], I),
+        "grim_index_load": ([ctypes.c_char_p, P, PP], I),
+        "grim_index_free": ([P], None),
+        "grim_filter_scan": ([P, ctypes.POINTER(_Reads), P, P, U32, P], I),
+        "grim_filter_candidates": ([P, ctypes.POINTER(_Reads), P, P, U64, P, P, P], I),
+        "grim_profile_enable": ([I], I),
+        "grim_profile_read": ([ctypes.POINTER(Profile), I], I),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != GRIM_OK:
+        raise GrimError(rc, lib().grim_last_error().decode(errors="replace"))
+
+
+# ---------------------------------------------------------------------------
+# pointer helpers: torch tensors (device) or numpy arrays (host)
+# ---------------------------------------------------------------------------
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if _is_torch(x):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return x.ctypes.data
+    raise TypeError(f"expected a torch tensor or numpy array, got {type(x)}")
+
+
+def _on_device(x) -> bool:
+    return _is_torch(x) and x.is_cuda
+
+
+def _check_dtype(x, name, np_dtype):
+    if x is None:
+        return
+    if _is_torch(x):
+        import torch
+        want = {np.uint8: torch.uint8, np.int64: torch.int64, np.uint16: torch.uint16, np.int32: torch.int32,
+                np.uint32: torch.uint32}[np_dtype]
+        if x.dtype != want:
+            raise TypeError(f"{name} must be {want}, got {x.dtype}")
+    elif x.dtype != np_dtype:
+        raise TypeError(f"{name} must be {np.dtype(np_dtype)}, got {x.dtype}")
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:
+            pass
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+@dataclass
+class ReadSet:
+    """A read set for the ABI: all arrays on the device (torch) or all on the host (numpy).
+
+    bases uint8 [n_bases]; offsets int64 [n+1]; optional max_edits / err_permille uint16 [n];
+    err_permille_all applies when neither per-read array is given.
+    """
+    bases: object
+    offsets: object
+    max_edits: object = None
+    err_permille: object = None
+    err_permille_all: int = 0
+    allow_short_overlap: bool = False
+
+    def _struct(self) -> _Reads:
+        arrs = [self.bases, self.offsets, self.max_edits, self.err_permille]
+        dev = [_on_device(a) for a in arrs if a is not None]
+        if any(dev) and not all(dev):
+            raise ValueError("read arrays must be all on the device or all on the host")
+        _check_dtype(self.bases, "bases", np.uint8)
+        _check_dtype(self.offsets, "offsets", np.int64)
+        _check_dtype(self.max_edits, "max_edits", np.uint16)
+        _check_dtype(self.err_permille, "err_permille", np.uint16)
+        n = len(self.offsets) - 1
+        r = _Reads()
+        r.bases = _ptr(self.bases)
+        r.offsets = _ptr(self.offsets)
+        r.n_reads = max(n, 0)
+        r.n_bases = len(self.bases)
+        r.max_edits = _ptr(self.max_edits)
+        r.err_permille = _ptr(self.err_permille)
+        r.err_permille_all = int(self.err_permille_all)
+        r.on_device = 1 if (dev and all(dev)) else 0
+        r.flags = READS_ALLOW_SHORT_OVERLAP if self.allow_short_overlap else 0
+        return r
+
+    @property
+    def n_reads(self) -> int:
+        return len(self.offsets) - 1
+
+
+class Index:
+    """A GRIM bit-vector index resident on one GPU (owns its device memory)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        out = IndexInfo()
+        _check(lib().grim_index_info(self._h, ctypes.byref(out)))
+        return out.as_dict()
+
+    def read(self, layout: int, offset: int = 0, nbytes: Optional[int] = None) -> np.ndarray:
+        inf = self.info()
+        size = inf["tm_bytes"] if layout == LAYOUT_TM else inf["bm_bytes"]
+        nbytes = size - offset if nbytes is None else nbytes
+        out = np.empty(nbytes, dtype=np.uint8)
+        _check(lib().grim_index_read(self._h, layout, offset, nbytes, out.ctypes.data))
+        return out
+
+    def save(self, path: str):
+        _check(lib().grim_index_save(self._h, path.encode()))
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib().grim_index_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def grim_build_index(ref, bin_size: int, overlap: int, q: int, layout: int = LAYOUT_TM,
+                     stream=None) -> Index:
+    """Build the per-bin token existence bits of ``ref`` (uint8 ASCII, torch or numpy)."""
+    _check_dtype(ref, "ref", np.uint8)
+    h = ctypes.c_void_p()
+    _check(lib().grim_build_index(_ptr(ref), len(ref), 1 if _on_device(ref) else 0, bin_size, overlap, q,
+                                  layout, _stream_handle(stream), ctypes.byref(h)))
+    return Index(h.value)
+
+
+def grim_index_load(path: str, stream=None) -> Index:
+    h = ctypes.c_void_p()
+    _check(lib().grim_index_load(path.encode(), _stream_handle(stream), ctypes.byref(h)))
+    return Index(h.value)
+
+
+def grim_filter_scan(index: Index, reads: ReadSet, mask_out, counts_out=None, stream=None):
+    """All-bins filter: pass mask [n][mask_words] uint32 (+ counts [n][n_bins] uint8/uint16)."""
+    _check_dtype(mask_out, "mask_out", np.uint32)
+    cb = 0
+    if counts_out is not None:
+        cb = counts_out.element_size() if _is_torch(counts_out) else counts_out.dtype.itemsize
+    r = reads._struct()
+    _check(lib().grim_filter_scan(index.handle, ctypes.byref(r), _ptr(mask_out), _ptr(counts_out), cb,
+                                  _stream_handle(stream)))
+
+
+def grim_filter_candidates(index: Index, reads: ReadSet, cand_off, cand_bin, count_out=None, pass_out=None,
+                           stream=None):
+    """Candidate filter: count [P] uint16 and pass [P] uint8 for each listed (read, bin)."""
+    _check_dtype(cand_off, "cand_off", np.int64)
+    _check_dtype(cand_bin, "cand_bin", np.int32)
+    _check_dtype(count_out, "count_out", np.uint16)
+    _check_dtype(pass_out, "pass_out", np.uint8)
+    r = reads._struct()
+    _check(lib().grim_filter_candidates(index.handle, ctypes.byref(r), _ptr(cand_off), _ptr(cand_bin),
+                                        len(cand_bin), _ptr(count_out), _ptr(pass_out),
+                                        _stream_handle(stream)))
+
+
+def grim_profile_enable(on: bool = True):
+    _check(lib().grim_profile_enable(1 if on else 0))
+
+
+def grim_profile_read(reset: bool = False) -> dict:
+    p = Profile()
+    _check(lib().grim_profile_read(ctypes.byref(p), 1 if reset else 0))
+    return {k: {"launches": getattr(p, k).launches, "total_ms": getattr(p, k).total_ms,
+                "last_ms": getattr(p, k).last_ms} for k, _ in Profile._fields_}
+
+
+def grim_abi_version() -> int:
+    return lib().grim_abi_version()

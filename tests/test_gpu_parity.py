@@ -1,0 +1,331 @@
+"""GPU path (through the C ABI) against the CPU oracle, element by element.
+
+Integer results, so the bar is bit-exact: index bits, per-bin counts, pass
+masks, candidate counts and pass flags. Sizes span several LDS tiles of the
+token-major index and several read chunks, with ragged tails."""
+
+from __future__ import annotations
+
+import os
+import random
+
+import numpy as np
+import pytest
+
+import synth
+import synth.configs as C
+from gpu_util import bm_to_bits, dev, empty, host, log, tm_to_bits, unpack_mask
+from paper_1708_04329_amd import grim
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    log("device", torch.cuda.get_device_name(0))
+    yield
+
+
+def rand_ref(rng: random.Random, G: int, n_runs: int = 4) -> np.ndarray:
+    ref = bytearray(rng.choice(b"ACGT") for _ in range(G))
+    for _ in range(n_runs):
+        p = rng.randrange(G)
+        ref[p:p + 3] = b"NNN"[:len(ref[p:p + 3])]
+    for _ in range(n_runs):
+        p = rng.randrange(G)
+        ref[p:p + 50] = bytes(ref[p:p + 50]).lower()
+    return np.frombuffer(bytes(ref[:G]), np.uint8).copy()
+
+
+def rand_reads(rng: random.Random, ref: np.ndarray, n: int, lmin: int, lmax: int):
+    seqs = []
+    G = len(ref)
+    for _ in range(n):
+        L = rng.randrange(lmin, lmax + 1)
+        if rng.random() < 0.8 and G > L:
+            p = rng.randrange(0, G - L)
+            s = bytearray(ref[p:p + L].tobytes())
+            for _ in range(rng.randrange(0, 8)):
+                s[rng.randrange(L)] = rng.choice(b"ACGTNacgt")
+        else:
+            s = bytearray(rng.choice(b"ACGT") for _ in range(L))
+        seqs.append(bytes(s))
+    return synth.reads_from_strings(seqs)
+
+
+def build(ref, B, O, q, layout=grim.LAYOUT_TM | grim.LAYOUT_BM):
+    return grim.grim_build_index(dev(ref), B, O, q, layout)
+
+
+def gpu_scan(idx, rd, counts_dtype=None, on_device=True, **kw):
+    import torch
+    info = idx.info()
+    n = rd.n
+    mask = empty((max(n, 1), info["mask_words"]), torch.uint32)
+    counts = empty((max(n, 1), info["n_bins"]), counts_dtype) if counts_dtype is not None else None
+    conv = dev if on_device else (lambda a: np.ascontiguousarray(a))
+    me = kw.pop("max_edits", None)
+    ep = kw.pop("err_permille", None)
+    rs = grim.ReadSet(conv(rd.bases) if len(rd.bases) else conv(np.zeros(1, np.uint8))[:0],
+                      conv(rd.offsets), None if me is None else conv(me),
+                      None if ep is None else conv(ep), **kw)
+    grim.grim_filter_scan(idx, rs, mask, counts)
+    torch.cuda.synchronize()
+    m = host(mask)[:n]
+    c = host(counts)[:n] if counts is not None else None
+    return m, c
+
+
+# ---------------------------------------------------------------------------
+# index bits
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5, 6, 7])
+def test_index_bits_match_oracle(oracle, q):
+    rng = random.Random(100 + q)
+    G = {1: 3000, 2: 5000, 3: 40000, 4: 60000, 5: 100000, 6: 60000, 7: 20000}[q]
+    B, O = 37, rng.randrange(0, 80)
+    ref = rand_ref(rng, G)
+    log("index bits q", q, "G", G, "B", B, "O", O)
+    idx = build(ref, B, O, q)
+    inf = idx.info()
+    want = oracle.bits(ref, B, O, q)
+    nb, R4 = want.shape
+    assert inf["n_bins"] == nb and inf["bits_bytes"] == oracle.index_bytes(nb, q)
+    tm = tm_to_bits(idx.read(grim.LAYOUT_TM), R4, inf["tm_row_words"], nb)
+    assert np.array_equal(tm, want)
+    bm = bm_to_bits(idx.read(grim.LAYOUT_BM), R4, inf["bm_vec_words"], nb)
+    assert np.array_equal(bm, want)
+    # padding of the token-major rows beyond the last bin is zero
+    rows = idx.read(grim.LAYOUT_TM).view("<u4").reshape(R4, inf["tm_row_words"])
+    tail = np.unpackbits(rows.view(np.uint8).reshape(R4, -1), axis=1, bitorder="little")[:, nb:]
+    assert not tail.any()
+
+
+# ---------------------------------------------------------------------------
+# all-bins scan
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(10))
+def test_scan_matches_oracle_random(oracle, seed, monkeypatch):
+    rng = random.Random(seed)
+    q = [3, 4, 5, 5, 6, 7, 5, 4, 6, 5][seed]
+    B = rng.choice([24, 32, 41, 64])
+    nb_target = {3: 1500, 4: 2100, 5: 2500, 6: 700, 7: 200}[q]
+    G = B * nb_target + rng.randrange(0, B)
+    O = rng.randrange(0, 120)
+    ref = rand_ref(rng, G)
+    n = rng.choice([1, 7, 130, 300])
+    lmax = 300 if seed % 3 == 0 else 120          # some reads above 255 tokens
+    rd = rand_reads(rng, ref, n, q, lmax)
+    mode = seed % 3
+    kw = {"allow_short_overlap": True}
+    if mode == 0:
+        kw["max_edits"] = np.array([rng.randrange(0, 12) for _ in range(n)], np.uint16)
+    elif mode == 1:
+        kw["err_permille"] = np.array([rng.choice([0, 20, 35, 50, 80]) for _ in range(n)], np.uint16)
+    else:
+        kw["err_permille_all"] = rng.choice([0, 25, 50])
+    monkeypatch.setenv("GRIM_SCAN_CHUNK", str(rng.choice([64, 128, 4096])))
+    monkeypatch.setenv("GRIM_SCAN_THREADS", str(rng.choice([256, 512, 1024])))
+    log("scan seed", seed, "q", q, "B", B, "G", G, "O", O, "n", n, "mode", mode,
+        os.environ["GRIM_SCAN_CHUNK"], os.environ["GRIM_SCAN_THREADS"])
+    idx = build(ref, B, O, q, grim.LAYOUT_TM)
+    bits = oracle.bits(ref, B, O, q)
+    nb = bits.shape[0]
+    want_c, want_p = oracle.scan_all(bits, q, rd.bases, rd.offsets, max_edits=kw.get("max_edits"),
+                                     err_pm_per_read=kw.get("err_permille"),
+                                     err_permille=kw.get("err_permille_all", 0))
+    m, c = gpu_scan(idx, rd, counts_dtype=__import__("torch").uint16, **kw)
+    assert np.array_equal(c.astype(np.uint16), want_c)
+    assert np.array_equal(unpack_mask(m, nb), want_p)
+    # mask bits beyond the last bin are zero
+    if nb % 32:
+        assert not (m[:, -1] >> (nb % 32)).any()
+
+
+def test_scan_c1_full_size(oracle):
+    """The 1 Mbp all-bins workload at its stated size: uint8 counts and pass bits."""
+    import torch
+    w = C.workload("c1")
+    ref = synth.genome(w.genome)
+    rd = synth.reads(w.reads, ref)
+    log("c1 full", len(ref), rd.n)
+    idx = build(ref, w.bin_size, w.overlap, w.q, grim.LAYOUT_TM)
+    E = np.full(rd.n, w.max_edits, np.uint16)
+    m, c = gpu_scan(idx, rd, counts_dtype=torch.uint8, max_edits=E)
+    bits = oracle.bits(ref, w.bin_size, w.overlap, w.q)
+    want_c, want_p = oracle.scan_all(bits, w.q, rd.bases, rd.offsets, max_edits=E)
+    assert np.array_equal(c, want_c.astype(np.uint8))
+    assert np.array_equal(unpack_mask(m, bits.shape[0]), want_p)
+    # every read (5 edits <= E) passes the bin of its true start
+    truth_bins = (rd.truth_pos // w.bin_size).astype(np.int64)
+    assert want_p[np.arange(rd.n), truth_bins].all()
+
+
+def test_host_inputs_equal_device_inputs(oracle):
+    import torch
+    rng = random.Random(42)
+    ref = rand_ref(rng, 70000)
+    rd = rand_reads(rng, ref, 200, 5, 150)
+    idx = build(ref, 50, 150, 5, grim.LAYOUT_TM)
+    E = np.array([rng.randrange(0, 6) for _ in range(rd.n)], np.uint16)
+    a = gpu_scan(idx, rd, counts_dtype=torch.uint16, max_edits=E, on_device=True)
+    b = gpu_scan(idx, rd, counts_dtype=torch.uint16, max_edits=E, on_device=False)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_threshold_not_positive_passes_all_bins(oracle):
+    rng = random.Random(9)
+    ref = rand_ref(rng, 40000)
+    rd = rand_reads(rng, ref, 50, 20, 60)
+    idx = build(ref, 64, 60, 5, grim.LAYOUT_TM)
+    nb = idx.info()["n_bins"]
+    m, _ = gpu_scan(idx, rd, max_edits=np.full(rd.n, 20, np.uint16), allow_short_overlap=True)
+    assert unpack_mask(m, nb).all()
+    if nb % 32:
+        assert not (m[:, -1] >> (nb % 32)).any()
+
+
+# ---------------------------------------------------------------------------
+# candidate mode
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("q", [2, 3, 4, 5, 6, 7])
+def test_candidates_match_oracle_random(oracle, q):
+    import torch
+    rng = random.Random(500 + q)
+    B = 61
+    G = 150000 if q <= 6 else 40000
+    ref = rand_ref(rng, G)
+    O = 200
+    idx = build(ref, B, O, q, grim.LAYOUT_BM)
+    nb = idx.info()["n_bins"]
+    rd = rand_reads(rng, ref, 257, q, 300)
+    # candidate lists: 0..200 bins per read, some reads with every bin
+    co, cb = [0], []
+    for r in range(rd.n):
+        k = rng.choice([0, 1, 3, 64, 65, 200])
+        if r % 50 == 7:
+            sel = list(range(nb))
+        else:
+            sel = sorted(rng.sample(range(nb), min(k, nb)))
+        cb += sel
+        co.append(len(cb))
+    co = np.array(co, np.int64)
+    cb = np.array(cb, np.int32)
+    err = np.array([rng.choice([20, 30, 40, 50]) for _ in range(rd.n)], np.uint16)
+    log("cand q", q, "pairs", len(cb))
+    cnt = empty((max(1, len(cb)),), torch.uint16)
+    pas = empty((max(1, len(cb)),), torch.uint8)
+    rs = grim.ReadSet(dev(rd.bases), dev(rd.offsets), err_permille=dev(err), allow_short_overlap=True)
+    grim.grim_filter_candidates(idx, rs, dev(co), dev(cb), cnt, pas)
+    bits = oracle.bits(ref, B, O, q)
+    wc, wp = oracle.scan_candidates(bits, q, rd.bases, rd.offsets, co, cb, err_pm_per_read=err)
+    assert np.array_equal(host(cnt)[:len(cb)], wc)
+    assert np.array_equal(host(pas)[:len(cb)], wp)
+
+
+def test_candidates_seed_hits_c2_recipe(oracle):
+    """The 100 Mbp candidate workload's recipe on a 4 Mbp genome with 20k reads."""
+    import torch
+    w = C.shrink(C.workload("c2"), genome_len=4_000_000, n_reads=20000)
+    ref = synth.genome(w.genome)
+    rd = synth.reads(w.reads, ref)
+    co, cb = synth.candidates(ref, rd, w.bin_size, w.cand_cap, w.cand_k)
+    log("c2-recipe pairs", len(cb))
+    idx = build(ref, w.bin_size, w.overlap, w.q, grim.LAYOUT_BM)
+    E = np.full(rd.n, w.max_edits, np.uint16)
+    cnt = empty((len(cb),), torch.uint16)
+    pas = empty((len(cb),), torch.uint8)
+    grim.grim_filter_candidates(idx, grim.ReadSet(dev(rd.bases), dev(rd.offsets), max_edits=dev(E)),
+                                dev(co), dev(cb), cnt, pas)
+    bits = oracle.bits(ref, w.bin_size, w.overlap, w.q)
+    wc, wp = oracle.scan_candidates(bits, w.q, rd.bases, rd.offsets, co, cb, max_edits=E)
+    assert np.array_equal(host(cnt), wc) and np.array_equal(host(pas), wp)
+
+
+def test_candidates_agree_with_scan():
+    import torch
+    rng = random.Random(77)
+    ref = rand_ref(rng, 90000)
+    B, O, q = 45, 120, 5
+    idx = build(ref, B, O, q)
+    nb = idx.info()["n_bins"]
+    rd = rand_reads(rng, ref, 100, 30, 100)
+    E = np.array([rng.randrange(0, 5) for _ in range(rd.n)], np.uint16)
+    m, c = gpu_scan(idx, rd, counts_dtype=torch.uint16, max_edits=E)
+    co = np.arange(rd.n + 1, dtype=np.int64) * nb
+    cb = np.tile(np.arange(nb, dtype=np.int32), rd.n)
+    cnt = empty((len(cb),), torch.uint16)
+    pas = empty((len(cb),), torch.uint8)
+    grim.grim_filter_candidates(idx, grim.ReadSet(dev(rd.bases), dev(rd.offsets), max_edits=dev(E)),
+                                dev(co), dev(cb), cnt, pas)
+    assert np.array_equal(host(cnt).reshape(rd.n, nb), c)
+    assert np.array_equal(host(pas).reshape(rd.n, nb), unpack_mask(m, nb))
+
+
+# ---------------------------------------------------------------------------
+# errors, empty inputs, persistence
+# ---------------------------------------------------------------------------
+
+def test_error_paths_leave_library_usable(oracle):
+    import torch
+    rng = random.Random(5)
+    ref = rand_ref(rng, 20000)
+    idx = build(ref, 100, 30, 5)
+    nb = idx.info()["n_bins"]
+    W = idx.info()["mask_words"]
+    mask = empty((4, W), torch.uint32)
+    # read shorter than q
+    rd = synth.reads_from_strings([b"ACG"])
+    with pytest.raises(grim.GrimError) as e:
+        grim.grim_filter_scan(idx, grim.ReadSet(dev(rd.bases), dev(rd.offsets)), mask)
+    assert e.value.code == grim.GRIM_EINVAL
+    # overlap too small for a 100 bp read at E = 5 (O = 30 < 100 + 5 - 5)
+    rd = synth.reads_from_strings([ref[:100].tobytes()])
+    with pytest.raises(grim.GrimError) as e:
+        grim.grim_filter_scan(idx, grim.ReadSet(dev(rd.bases), dev(rd.offsets), max_edits=dev(np.array([5], np.uint16))), mask)
+    assert e.value.code == grim.GRIM_EOVERLAP
+    # uint8 counts with more than 255 tokens
+    rd = synth.reads_from_strings([ref[:400].tobytes()])
+    cnt8 = empty((1, nb), torch.uint8)
+    with pytest.raises(grim.GrimError) as e:
+        grim.grim_filter_scan(idx, grim.ReadSet(dev(rd.bases), dev(rd.offsets), allow_short_overlap=True), mask, cnt8)
+    assert e.value.code == grim.GRIM_EINVAL
+    # candidate bin out of range
+    rd = synth.reads_from_strings([ref[:30].tobytes()])
+    with pytest.raises(grim.GrimError) as e:
+        grim.grim_filter_candidates(idx, grim.ReadSet(dev(rd.bases), dev(rd.offsets)), dev(np.array([0, 2], np.int64)),
+                                    dev(np.array([0, nb], np.int32)), empty((2,), torch.uint16), empty((2,), torch.uint8))
+    assert e.value.code == grim.GRIM_EINVAL
+    # empty read set is a no-op
+    grim.grim_filter_scan(idx, grim.ReadSet(dev(np.zeros(1, np.uint8)), dev(np.zeros(1, np.int64))), mask)
+    # and a good call still works afterwards
+    rd = synth.reads_from_strings([ref[1000:1030].tobytes()])
+    m, _ = gpu_scan(idx, rd, max_edits=np.array([0], np.uint16))
+    bits = oracle.bits(ref, 100, 30, 5)
+    _, wp = oracle.scan_all(bits, 5, rd.bases, rd.offsets, max_edits=np.array([0], np.uint16))
+    assert np.array_equal(unpack_mask(m, nb), wp)
+
+
+def test_save_load_roundtrip(tmp_path):
+    import torch
+    rng = random.Random(6)
+    ref = rand_ref(rng, 50000)
+    idx = build(ref, 80, 100, 5)
+    p = str(tmp_path / "i.grim")
+    idx.save(p)
+    idx2 = grim.grim_index_load(p)
+    assert idx2.info() == idx.info()
+    assert np.array_equal(idx2.read(grim.LAYOUT_TM), idx.read(grim.LAYOUT_TM))
+    assert np.array_equal(idx2.read(grim.LAYOUT_BM), idx.read(grim.LAYOUT_BM))
+    raw = bytearray(open(p, "rb").read())
+    raw[-5] ^= 0xFF
+    bad = str(tmp_path / "bad.grim")
+    open(bad, "wb").write(bytes(raw))
+    with pytest.raises(grim.GrimError) as e:
+        grim.grim_index_load(bad)
+    assert e.value.code == grim.GRIM_EIO
