@@ -1,0 +1,290 @@
+"""GRIM-Filter hot-path benchmark on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
+
+A step is one pass of the whole hot path over one batch of synthetic reads:
+tokenisation and per-read thresholds, then the filter (all-bins scan or
+candidate checks), with reads and index already resident in HBM. The default
+workload is the human-scale all-bins scan: a 3.1 Gbp synthetic genome with 45%
+repeats, 2048 bp bins (1,513,672 bins), q = 5, and 1M reads of 150 bp with
+E = 7. Prints one JSON line.
+
+Besides the step time it reports, for the dominant kernel, the roofline
+position (kernel time from HIP events recorded by the library on the stream it
+launches on) and a CPU baseline: the plain CPU oracle timed on a bounded sample
+of the same workload on this host's cores, whose results are also checked
+bit-exactly against the GPU output for the same reads.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "read×bin checks/s (bit-exact) + served reads/s & p99 latency vs plain launch"
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 int32 lane-ops/s.
+# A full adder on 32 bins is two lane-ops (v_bitop3 xor3 + majority), so one
+# lane-op advances at most 16 bit-accumulations.
+ALU_LANE_OPS = 256 * 64 * 2.4e9
+BITACC_PEAK = ALU_LANE_OPS * 32 / 2
+HBM_PEAK = 8.0e12
+
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs (scaled by a 1 GiB copy kernel), keyed by the sha256 of the kernel source
+# they were taken on; reported as null once the source has changed since.
+MEASURED_TRAFFIC = {
+    ("c3_allbins_3.1Gbp_q5", "scan_allbins.hip"): {
+        "sha256": "a322579ada87b353f9fa24a8a440d5c9e601cb415c08a6d0a9ca2610130944b1", "fetch_bytes": 66.8e9, "write_bytes": 190.7e9,
+        "profile": "profiles/k_scan_allbins_c3_3.1Gbp_q5.md"},
+}
+
+
+def measured_traffic(workload: str, src: str):
+    import hashlib
+    ent = MEASURED_TRAFFIC.get((workload, src))
+    if not ent:
+        return None
+    path = os.path.join(ROOT, "paper_1708_04329_amd", "csrc", src)
+    sha = hashlib.sha256(open(path, "rb").read()).hexdigest()
+    if sha != ent["sha256"]:
+        return None
+    return ent["fetch_bytes"] + ent["write_bytes"]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
+    p.add_argument("--reads-scale", type=float, default=1.0, help="fraction of the stated read count (testing only)")
+    p.add_argument("--genome-len", type=int, default=0, help="override genome length (testing only)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
+    p.add_argument("--calib-copy-mb", type=int, default=0,
+                   help="run one plain device copy of this many MiB before timing (HBM counter calibration)")
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(bins or reads would shard across GPUs without any collective; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import synth.configs as C
+    from paper_1708_04329_amd import grim
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = C.workload(args.workload, scale=args.reads_scale)
+    if args.genome_len:
+        w = C.shrink(w, genome_len=args.genome_len)
+
+    t0 = time.time()
+    ref = synth.genome(w.genome)
+    log(f"genome {len(ref):,} bp in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    rd = synth.reads(w.reads, ref)
+    log(f"{rd.n:,} reads in {time.time() - t0:.1f}s")
+    cand = None
+    if w.mode == "candidates":
+        t0 = time.time()
+        cand = synth.candidates(ref, rd, w.bin_size, w.cand_cap, w.cand_k)
+        log(f"{len(cand[1]):,} seed-hit candidates in {time.time() - t0:.1f}s")
+
+    stream = torch.cuda.current_stream()
+    layout = grim.LAYOUT_TM if w.mode == "allbins" else grim.LAYOUT_BM
+    dref = torch.from_numpy(ref).cuda()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    idx = grim.grim_build_index(dref, w.bin_size, w.overlap, w.q, layout, stream)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    del dref
+    info = idx.info()
+    nb, W = info["n_bins"], info["mask_words"]
+    log(f"index: {nb:,} bins, {(info['tm_bytes'] + info['bm_bytes']) / 1e6:.1f} MB, built in {build_s:.2f}s")
+
+    n = rd.n
+    lens = rd.lengths
+    d_bases = torch.from_numpy(rd.bases).cuda()
+    d_offs = torch.from_numpy(rd.offsets).cuda()
+    me = ep = None
+    if w.max_edits is not None:
+        me = np.full(n, w.max_edits, np.uint16)
+    elif w.per_read_error:
+        ep = rd.err_pm.astype(np.uint16)
+    reads = grim.ReadSet(d_bases, d_offs,
+                         max_edits=None if me is None else torch.from_numpy(me).cuda(),
+                         err_permille=None if ep is None else torch.from_numpy(ep).cuda())
+    q = w.q
+    tokens_total = int(np.sum(lens - q + 1))
+
+    if w.mode == "allbins":
+        mask = torch.empty((n, W), dtype=torch.uint32, device="cuda")
+        checks = n * nb
+        work_units = tokens_total * nb                     # bit-accumulations per step
+        kernel_key = "scan"
+
+        def step():
+            grim.grim_filter_scan(idx, reads, mask, None, stream)
+    else:
+        co, cb = cand
+        d_co = torch.from_numpy(co).cuda()
+        d_cb = torch.from_numpy(cb).cuda()
+        P = len(cb)
+        cnt = torch.empty(max(P, 1), dtype=torch.uint16, device="cuda")
+        pas = torch.empty(max(P, 1), dtype=torch.uint8, device="cuda")
+        checks = P
+        vec_bytes = info["bm_vec_words"] * 4
+        work_units = P * (vec_bytes + 4 + 2 + 1)           # gathered vector + bin id + outputs
+        kernel_key = "candidates"
+
+        def step():
+            grim.grim_filter_candidates(idx, reads, d_co, d_cb, cnt, pas, stream)
+
+    if args.calib_copy_mb:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale the
+        # counters of the filter kernels to bytes
+        src = torch.empty(args.calib_copy_mb << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    grim.grim_profile_enable(True)
+    grim.grim_profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        log(f"step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = grim.grim_profile_read(reset=True)
+    grim.grim_profile_enable(False)
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = checks * args.steps / elapsed
+    kt = prof[kernel_key]
+    avg_ms = kt["total_ms"] / max(1, kt["launches"])
+    if w.mode == "allbins":
+        achieved = work_units / (avg_ms * 1e-3)
+        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": BITACC_PEAK / 1e12,
+                    "unit": "Tbit-acc/s", "frac": achieved / BITACC_PEAK,
+                    "traffic": measured_traffic(w.name, "scan_allbins.hip"),
+                    "kernel": "k_scan_allbins", "avg_launch_ms": avg_ms,
+                    "work_per_launch": f"{work_units:.4g} bit-accumulations (tokens x bins)"}
+    else:
+        achieved = work_units / (avg_ms * 1e-3)
+        roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK, "traffic": measured_traffic(w.name, "scan_candidates.hip"),
+                    "kernel": "k_scan_cand",
+                    "avg_launch_ms": avg_ms, "work_per_launch": f"{work_units:.4g} algorithmic bytes"}
+    log(f"{ms_per_step:.2f} ms/step, {value:.4g} checks/s; kernel {avg_ms:.2f} ms, "
+        f"roofline frac {roofline['frac']:.3f}")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "checks/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": w.name, "mode": w.mode, "genome_bp": len(ref), "bin_size": w.bin_size,
+                   "overlap": w.overlap, "q": q, "n_bins": nb, "reads": n,
+                   "read_len": sorted(set(int(x) for x in np.unique(lens))), "checks_per_step": checks,
+                   "max_edits": w.max_edits, "per_read_error": w.per_read_error,
+                   "index_bytes": info["tm_bytes"] + info["bm_bytes"], "index_build_s": round(build_s, 3)},
+        "reads_per_s": n * args.steps / elapsed,
+        "tokenize_avg_ms": prof["tokenize"]["total_ms"] / max(1, prof["tokenize"]["launches"]),
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, w, ref, rd, me, ep, idx, info, cand, mask if w.mode == "allbins"
+                                           else (cnt, pas))
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(args, w, ref, rd, me, ep, idx, info, cand, gpu_out):
+    """Time the CPU oracle on a bounded sample and check it against the GPU output."""
+    import torch
+    from oracle import Oracle
+    o = Oracle()
+    threads = o.threads_used()
+    t0 = time.time()
+    bits = o.bits(ref, w.bin_size, w.overlap, w.q)
+    log(f"oracle bit vectors in {time.time() - t0:.1f}s ({threads} threads)")
+    rng = np.random.default_rng(1234)
+    n = rd.n
+    nb = info["n_bins"]
+
+    def sample(k):
+        return np.sort(rng.choice(n, size=min(k, n), replace=False))
+
+    if w.mode == "allbins":
+        def run(ids):
+            sub = rd.subset(ids)
+            t = time.perf_counter()
+            _, p = o.scan_all(bits, w.q, sub.bases, sub.offsets, max_edits=None if me is None else me[ids],
+                              err_pm_per_read=None if ep is None else ep[ids], want_counts=False)
+            return time.perf_counter() - t, p
+        k = 2
+        dt, _ = run(sample(k))
+        k = int(max(2, min(n, k * args.cpu_seconds / max(dt, 1e-3))))
+        ids = sample(k)
+        dt, p = run(ids)
+        checks = len(ids) * nb
+        got = gpu_out.view(torch.int32)[torch.from_numpy(ids).cuda()].cpu().numpy().view(np.uint32)
+        gp = np.unpackbits(got.view(np.uint8).reshape(len(ids), -1), axis=1, bitorder="little")[:, :nb]
+        exact = bool(np.array_equal(gp, p))
+        desc = f"{len(ids)} reads (seeded sample) x all {nb} bins"
+    else:
+        co, cb = cand
+        cnt, pas = gpu_out
+
+        def run(ids):
+            sub = rd.subset(ids)
+            sco = np.zeros(len(ids) + 1, np.int64)
+            sco[1:] = np.cumsum(co[ids + 1] - co[ids])
+            scb = np.concatenate([cb[co[i]:co[i + 1]] for i in ids]) if len(ids) else np.zeros(0, np.int32)
+            t = time.perf_counter()
+            c, p = o.scan_candidates(bits, w.q, sub.bases, sub.offsets, sco, scb,
+                                     max_edits=None if me is None else me[ids],
+                                     err_pm_per_read=None if ep is None else ep[ids])
+            return time.perf_counter() - t, (c, p, sco)
+        k = 1000
+        dt, _ = run(sample(k))
+        k = int(max(1000, min(n, k * args.cpu_seconds / max(dt, 1e-3))))
+        ids = sample(k)
+        dt, (c, p, sco) = run(ids)
+        checks = int(sco[-1])
+        sel = np.concatenate([np.arange(co[i], co[i + 1]) for i in ids])
+        tsel = torch.from_numpy(sel).cuda()
+        exact = bool(np.array_equal(cnt[tsel].cpu().numpy(), c) and np.array_equal(pas[tsel].cpu().numpy(), p))
+        desc = f"{len(ids)} reads (seeded sample), {checks} candidate pairs"
+    log(f"oracle: {checks:,} checks in {dt:.1f}s; GPU rows bit-exact: {exact}")
+    return {"value": checks / dt, "unit": "checks/s", "cores": threads, "kind": "oracle", "sample": desc,
+            "seconds": dt, "gpu_bit_exact_on_sample": exact}
+
+
+if __name__ == "__main__":
+    main()
