@@ -178,7 +178,7 @@ int check_reads_args(const grim_index* idx, const grim_reads* rd) {
 
 // Tokenise + thresholds into the index workspace; leaves status zeroed first.
 int tokenize_reads(grim_index* idx, const grim_reads* rd, const ReadView& v, uint32_t max_tokens,
-                   hipStream_t s, ProfSpan& ps) {
+                   uint32_t tok_shift, hipStream_t s, ProfSpan& ps) {
   grim_workspace& ws = idx->ws;
   int rc = ensure_status(ws);
   if (rc) return rc;
@@ -199,6 +199,7 @@ int tokenize_reads(grim_index* idx, const grim_reads* rd, const ReadView& v, uin
   a.overlap = idx->O;
   a.flags = rd->flags;
   a.max_tokens = max_tokens;
+  a.tok_shift = tok_shift;
   a.tokens = ws.tokens;
   a.thr = ws.thr;
   a.status = ws.status;
@@ -219,7 +220,9 @@ ScanConfig scan_config_from_env() {
   ScanConfig c;
   if (const char* t = std::getenv("GRIM_SCAN_THREADS")) c.threads = std::atoi(t);
   if (const char* t = std::getenv("GRIM_SCAN_CHUNK")) c.reads_per_chunk = std::atoi(t);
-  if (c.threads != 256 && c.threads != 512 && c.threads != 1024) c.threads = 512;
+  if (const char* t = std::getenv("GRIM_SCAN_LANE_WORDS")) c.lane_words = std::atoi(t);
+  if (c.threads != 256 && c.threads != 512 && c.threads != 1024) c.threads = 1024;
+  if (c.lane_words != 4 && c.lane_words != 8) c.lane_words = 4;
   if (c.reads_per_chunk < 64) c.reads_per_chunk = 64;
   return c;
 }
@@ -506,7 +509,8 @@ int grim_filter_scan(const grim_index* cidx, const grim_reads* rd, uint32_t* mas
   rc = stage_reads(idx, rd, s, &v);
   if (rc) return rc;
   ProfSpan pt(PROF_TOKENIZE);
-  rc = tokenize_reads(idx, rd, v, counts_out && counts_bytes == 1 ? 255u : 65535u, s, pt);
+  rc = tokenize_reads(idx, rd, v, counts_out && counts_bytes == 1 ? 255u : 65535u, scan_token_shift(idx->q), s,
+                      pt);
   if (rc) return rc;
   ScanArgs a{};
   a.tm = idx->tm;
@@ -552,7 +556,7 @@ int grim_filter_candidates(const grim_index* cidx, const grim_reads* rd, const i
   rc = stage_reads(idx, rd, s, &v);
   if (rc) return rc;
   ProfSpan pt(PROF_TOKENIZE);
-  rc = tokenize_reads(idx, rd, v, 65535u, s, pt);
+  rc = tokenize_reads(idx, rd, v, 65535u, 0u, s, pt);
   if (rc) return rc;
   CandArgs a{};
   a.bm = idx->bm;

@@ -37,8 +37,11 @@ enum : uint32_t {
 };
 int status_to_error(uint32_t st);
 
-// Token storage: read r's tokens start at token_base(offsets[r], r) (a multiple
-// of 32 tokens) and are padded with the code R4 = 4^q up to a multiple of 32.
+// Token storage: uint32 per token. Read r's tokens start at
+// token_base(offsets[r], r) (a multiple of 32 tokens) and are padded with the
+// code R4 = 4^q up to a multiple of 32. Each entry holds code << tok_shift: the
+// all-bins scan stores the LDS byte offset of the token's row (shift =
+// log2(tile words * 4)), candidate checks store the plain code (shift 0).
 // The regions of consecutive reads never overlap, and the buffer needs
 // token_capacity(n_bases, n_reads) entries.
 __host__ __device__ inline uint64_t token_base(int64_t off, uint64_t r) {
@@ -68,7 +71,8 @@ struct TokArgs {
   uint32_t overlap;
   uint32_t flags;
   uint32_t max_tokens;  // 255 when uint8 counts are requested, else 65535
-  uint16_t* tokens;
+  uint32_t tok_shift;   // tokens are stored as code << tok_shift
+  uint32_t* tokens;
   int32_t* thr;
   uint32_t* status;
 };
@@ -94,7 +98,7 @@ struct ScanArgs {
   uint32_t q;
   uint64_t nb;
   uint64_t W;
-  const uint16_t* tokens;
+  const uint32_t* tokens;      // code << log2(TW * 4): LDS byte offset of the row
   const int64_t* offsets;
   const int32_t* thr;
   const uint32_t* read_order;  // chunk position -> read index, or null for identity
@@ -108,9 +112,15 @@ struct ScanArgs {
   const uint32_t* status;
 };
 struct ScanConfig {
-  int threads = 512;          // threads per workgroup
+  int threads = 1024;         // threads per workgroup (16 waves: 4 per SIMD)
   int reads_per_chunk = 4096; // reads per workgroup
+  int lane_words = 4;         // uint32 words (x32 bins) per lane: 4 or 8
 };
+// Shift that turns a token code into the LDS byte offset of its tile row.
+inline uint32_t scan_token_shift(uint32_t q) {
+  const int tw = tm_tile_words(q);
+  return tw == 32 ? 7u : (tw == 8 ? 5u : 3u);
+}
 hipError_t launch_scan_allbins(const ScanArgs& a, const ScanConfig& cfg, hipStream_t s);
 
 struct CandArgs {
@@ -119,7 +129,7 @@ struct CandArgs {
   uint32_t R4;
   uint32_t q;
   uint64_t nb;
-  const uint16_t* tokens;
+  const uint32_t* tokens;      // plain codes (shift 0)
   const int64_t* offsets;
   const int32_t* thr;
   uint64_t n_reads;
@@ -156,7 +166,7 @@ struct ProfSpan {
 // The index handle.
 // ---------------------------------------------------------------------------
 struct grim_workspace {
-  uint16_t* tokens = nullptr;
+  uint32_t* tokens = nullptr;
   uint64_t tokens_cap = 0;
   int32_t* thr = nullptr;
   uint64_t thr_cap = 0;

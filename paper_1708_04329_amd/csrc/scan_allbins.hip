@@ -9,15 +9,19 @@
 // are folded in with a carry-save (Harley-Seal) tree of full adders; on gfx950
 // a full adder is two v_bitop3_b32 instructions (xor3 for the sum, majority
 // for the carry), so each token costs about two VALU operations per 32 bins.
-// The threshold test is a bit-serial comparison of the planes against T_r.
+// The threshold test adds K = 2^P - T_r to the P-plane counters and keeps the
+// carry out of the top plane (count >= T_r exactly when that carry is 1): one
+// majority per plane.
 //
 // Work split: a workgroup owns one tile of TW words (32*TW bins) and a chunk
 // of reads. It copies the tile's 4^q rows (plus an all-zero row for invalid
 // and padding tokens) from HBM into LDS once, then every read of the chunk
 // streams its token list against the LDS rows: G = TW/LW lanes share a read,
-// each lane owns LW words (32*LW bins) and reads them with one LDS load per
-// token. Workgroup ids are remapped so the 32 CUs of one XCD work on the
-// tiles of the same read chunk, whose tokens then stay in that XCD's L2.
+// each lane owns LW words (32*LW bins) and reads them with LW/4 16-byte LDS
+// loads per token. Tokens arrive pre-scaled to the LDS byte offset of their
+// row, so a row address costs one add per token. Workgroup ids are remapped
+// so the 32 CUs of one XCD work on the tiles of the same read chunk, whose
+// tokens then stay in that XCD's L2.
 
 #include "grim_internal.h"
 
@@ -48,7 +52,12 @@ struct Words {
 template <int LW>
 __device__ __forceinline__ Words<LW> lds_row(const uint32_t* p) {
   Words<LW> r;
-  if constexpr (LW == 4) {
+  if constexpr (LW == 8) {
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    const uint4 u = *reinterpret_cast<const uint4*>(p + 4);
+    r.w[0] = v.x; r.w[1] = v.y; r.w[2] = v.z; r.w[3] = v.w;
+    r.w[4] = u.x; r.w[5] = u.y; r.w[6] = u.z; r.w[7] = u.w;
+  } else if constexpr (LW == 4) {
     const uint4 v = *reinterpret_cast<const uint4*>(p);
     r.w[0] = v.x; r.w[1] = v.y; r.w[2] = v.z; r.w[3] = v.w;
   } else if constexpr (LW == 2) {
@@ -68,12 +77,11 @@ struct Counters {
   uint32_t p[5 + NHI][LW];
 };
 
-// Fold 32 tokens (codes in tok[0..15] as packed uint16 pairs) into the counters.
-template <int TW, int LW, int NHI>
-__device__ __forceinline__ void fold32(Counters<LW, NHI>& c, const uint32_t* lds_lane, const uint32_t (&tk)[16]) {
+// Fold 32 tokens (tk[i] = LDS byte offset of token i's row) into the counters.
+template <int LW, int NHI>
+__device__ __forceinline__ void fold32(Counters<LW, NHI>& c, const char* lds_lane, const uint32_t (&tk)[32]) {
   auto row = [&](int i) -> Words<LW> {
-    const uint32_t code = (tk[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu;
-    return lds_row<LW>(lds_lane + code * TW);
+    return lds_row<LW>(reinterpret_cast<const uint32_t*>(lds_lane + tk[i]));
   };
   uint32_t s16a[LW], s16b[LW];
 #pragma unroll
@@ -100,6 +108,10 @@ __device__ __forceinline__ void fold32(Counters<LW, NHI>& c, const uint32_t* lds
         if (h8 == 0) CSA(e8a[j], c.p[2][j], c.p[2][j], f4a[j], f4b[j]);
         else CSA(e8b[j], c.p[2][j], c.p[2][j], f4a[j], f4b[j]);
       }
+      // keep the scheduler from hoisting the next 8 tokens' LDS loads above
+      // this point: with 8 words per lane, 32 tokens of loads in flight would
+      // not fit the register file
+      if constexpr (LW >= 8) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int j = 0; j < LW; ++j) {
@@ -121,27 +133,22 @@ __device__ __forceinline__ void fold32(Counters<LW, NHI>& c, const uint32_t* lds
   }
 }
 
-// Bit-serial comparison of 32 bit-sliced counters with T: bit b of the
-// result is (counter_b >= T).
+// Threshold test on 32 bit-sliced counters of NP planes: bit b of the result
+// is (counter_b >= T). With K = 2^NP - T the counter reaches T exactly when
+// counter + K carries out of plane NP-1; the carry chain is one majority per
+// plane (km[k] = all-ones when bit k of K is set). T <= 0 passes every bin.
 template <int NP>
-__device__ __forceinline__ uint32_t ge_threshold(const uint32_t (&pl)[NP], int32_t T) {
-  if (T <= 0) return 0xFFFFFFFFu;
-  const uint32_t U = (uint32_t)(T - 1);  // count >= T  <=>  count > U
-  uint32_t gt = 0, eq = 0xFFFFFFFFu;
+__device__ __forceinline__ uint32_t ge_threshold(const uint32_t (&pl)[NP], const uint32_t (&km)[NP],
+                                                 uint32_t allpass) {
+  uint32_t carry = pl[0] & km[0];
 #pragma unroll
-  for (int k = NP - 1; k >= 0; --k) {
-    const uint32_t u = ((U >> k) & 1u) ? 0xFFFFFFFFu : 0u;
-    gt |= eq & pl[k] & ~u;
-    eq &= ~(pl[k] ^ u);
-  }
-  if (NP < 32 && (U >> NP) != 0) return 0;  // T beyond the counter range
-  return gt;
+  for (int k = 1; k < NP; ++k) carry = maj3(pl[k], km[k], carry);
+  return carry | allpass;
 }
 
-template <int TW, int LW, int NHI>
-__device__ __forceinline__ void scan_read(const ScanArgs& a, const uint32_t* lds_lane, bool active,
-                                          uint64_t rid, uint32_t ntok, uint64_t tbase, int32_t T,
-                                          uint64_t gw0) {
+template <int LW, int NHI>
+__device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lane, bool active, uint64_t rid,
+                                          uint32_t ntok, uint64_t tbase, int32_t T, uint64_t gw0) {
   constexpr int NP = 5 + NHI;
   Counters<LW, NHI> c;
 #pragma unroll
@@ -151,15 +158,21 @@ __device__ __forceinline__ void scan_read(const ScanArgs& a, const uint32_t* lds
   const uint32_t nblk = active ? (ntok + 31) >> 5 : 0;
   const uint4* tk4 = reinterpret_cast<const uint4*>(a.tokens + tbase);
   for (uint32_t b = 0; b < nblk; ++b) {
-    uint32_t tk[16];
+    uint32_t tk[32];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint4 v = tk4[b * 4 + i];
+    for (int i = 0; i < 8; ++i) {
+      const uint4 v = tk4[b * 8 + i];
       tk[4 * i + 0] = v.x; tk[4 * i + 1] = v.y; tk[4 * i + 2] = v.z; tk[4 * i + 3] = v.w;
     }
-    fold32<TW, LW, NHI>(c, lds_lane, tk);
+    fold32<LW, NHI>(c, lds_lane, tk);
   }
   if (!active) return;
+  // K = 2^NP - T as NP all-ones/all-zeros masks, shared by the lane's words
+  const uint32_t allpass = T <= 0 ? 0xFFFFFFFFu : 0u;
+  const uint32_t K = T <= 0 ? 0u : (uint32_t)((1u << NP) - (uint32_t)T);
+  uint32_t km[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) km[k] = ((K >> k) & 1u) ? 0xFFFFFFFFu : 0u;
 #pragma unroll
   for (int j = 0; j < LW; ++j) {
     const uint64_t gw = gw0 + j;
@@ -167,7 +180,7 @@ __device__ __forceinline__ void scan_read(const ScanArgs& a, const uint32_t* lds
     uint32_t pl[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) pl[k] = c.p[k][j];
-    uint32_t ge = ge_threshold<NP>(pl, T);
+    uint32_t ge = ge_threshold<NP>(pl, km, allpass);
     if (gw == a.W - 1 && (a.nb & 31)) ge &= (1u << (a.nb & 31)) - 1u;
     a.mask_out[rid * a.W + gw] = ge;
     if (a.counts_out) {
@@ -224,7 +237,7 @@ __global__ __launch_bounds__(NT) void k_scan_allbins(ScanArgs a) {
 
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const uint32_t g = lane / G, s = lane % G;
-  const uint32_t* lds_lane = lds + s * LW;
+  const char* lds_lane = reinterpret_cast<const char*>(lds) + s * LW * 4;
   const uint64_t gw0 = (uint64_t)tile * TW + (uint64_t)s * LW;
   const uint64_t r_begin = (uint64_t)rchunk * a.reads_per_chunk;
   uint64_t r_end = r_begin + a.reads_per_chunk;
@@ -243,8 +256,8 @@ __global__ __launch_bounds__(NT) void k_scan_allbins(ScanArgs a) {
       tbase = token_base(o0, rid);
       T = a.thr[rid];
     }
-    if (__any(ntok > 255)) scan_read<TW, LW, 11>(a, lds_lane, active, rid, ntok, tbase, T, gw0);
-    else scan_read<TW, LW, 3>(a, lds_lane, active, rid, ntok, tbase, T, gw0);
+    if (__any(ntok > 255)) scan_read<LW, 11>(a, lds_lane, active, rid, ntok, tbase, T, gw0);
+    else scan_read<LW, 3>(a, lds_lane, active, rid, ntok, tbase, T, gw0);
   }
 }
 
@@ -268,20 +281,24 @@ hipError_t launch_scan_allbins(const ScanArgs& a0, const ScanConfig& cfg, hipStr
   a.n_rchunks = (uint32_t)((a.n_reads + a.reads_per_chunk - 1) / a.reads_per_chunk);
   if (a.n_reads == 0 || a.n_tiles == 0) return hipSuccess;
   const int nt = cfg.threads;
+  const bool w8 = cfg.lane_words == 8;
+#define GRIM_SCAN_NT(TW_, LW_)                                              \
+  do {                                                                      \
+    if (nt == 1024) return launch_t<TW_, LW_, 1024>(a, s);                  \
+    if (nt == 256) return launch_t<TW_, LW_, 256>(a, s);                    \
+    return launch_t<TW_, LW_, 512>(a, s);                                   \
+  } while (0)
   switch (TW) {
     case 32:
-      if (nt == 1024) return launch_t<32, 4, 1024>(a, s);
-      if (nt == 256) return launch_t<32, 4, 256>(a, s);
-      return launch_t<32, 4, 512>(a, s);
+      if (w8) GRIM_SCAN_NT(32, 8);
+      GRIM_SCAN_NT(32, 4);
     case 8:
-      if (nt == 1024) return launch_t<8, 4, 1024>(a, s);
-      if (nt == 256) return launch_t<8, 4, 256>(a, s);
-      return launch_t<8, 4, 512>(a, s);
+      if (w8) GRIM_SCAN_NT(8, 8);
+      GRIM_SCAN_NT(8, 4);
     default:
-      if (nt == 1024) return launch_t<2, 2, 1024>(a, s);
-      if (nt == 256) return launch_t<2, 2, 256>(a, s);
-      return launch_t<2, 2, 512>(a, s);
+      GRIM_SCAN_NT(2, 2);
   }
+#undef GRIM_SCAN_NT
 }
 
 }  // namespace grim

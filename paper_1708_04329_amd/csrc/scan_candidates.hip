@@ -44,7 +44,7 @@ __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
   if (c0 == c1) return;
   const int64_t o0 = a.offsets[r], o1 = a.offsets[r + 1];
   const uint32_t ntok = (uint32_t)(o1 - o0 - a.q + 1);
-  const uint16_t* tok = a.tokens + token_base(o0, r);
+  const uint32_t* tok = a.tokens + token_base(o0, r);
   const int32_t T = a.thr[r];
   const uint32_t R4 = a.R4;
 

@@ -8,6 +8,9 @@
 // error budget E_r = ceil(e_r * L_r) (Section 6, read-existence figure
 // caption) are computed here too, one per read.
 //
+// Tokens are written as code << tok_shift (the scan kernel wants the LDS byte
+// offset of the token's row, the candidate kernel the plain code).
+//
 // One wavefront per read: lane l writes tokens l, l + 64, ... so stores are
 // coalesced; each token re-reads its q bases, which stay in L1/L2.
 
@@ -55,7 +58,7 @@ __global__ __launch_bounds__(256) void k_tokenize(TokArgs a) {
   if (err & (ST_BAD_LENGTH | ST_TOO_LONG)) return;
   const uint32_t R4 = 1u << (2 * q);
   const uint8_t* rd = a.bases + o0;
-  uint16_t* out = a.tokens + token_base(o0, r);
+  uint32_t* out = a.tokens + token_base(o0, r);
   const int64_t npad = (ntok + 31) & ~31ll;
   for (int64_t i = lane; i < npad; i += 64) {
     uint32_t code = R4;
@@ -69,7 +72,7 @@ __global__ __launch_bounds__(256) void k_tokenize(TokArgs a) {
       }
       if (ok) code = c;
     }
-    out[i] = (uint16_t)code;
+    out[i] = code << a.tok_shift;
   }
 }
 
