@@ -172,6 +172,92 @@ int grim_filter_candidates(const grim_index* idx, const grim_reads* reads,
                            const int64_t* cand_off, const int32_t* cand_bin, uint64_t n_cand,
                            uint16_t* count_out, uint8_t* pass_out, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Batching layer: launch-shape tuning and a graph-captured steady-state loop.
+ * Both drive the same kernels as grim_filter_scan / grim_filter_candidates;
+ * the arithmetic (and therefore every output bit) is unchanged.
+ * ---------------------------------------------------------------------- */
+#define GRIM_MODE_SCAN 1u       /* all-bins filter */
+#define GRIM_MODE_CANDIDATES 2u /* candidate-location filter */
+
+/* A launch shape and, after grim_tune, its measured kernel time. */
+typedef struct {
+  uint32_t mode;               /* GRIM_MODE_* the fields below apply to */
+  uint32_t threads;            /* all-bins: threads per workgroup (256, 512, 1024) */
+  uint32_t reads_per_chunk;    /* all-bins: reads per workgroup, i.e. per LDS tile reuse (>= 64) */
+  uint32_t lane_words;         /* all-bins: uint32 words = 32-bin groups per lane (4 or 8) */
+  uint32_t cand_waves;         /* candidates: wavefronts per workgroup (0 = by vector size) */
+  uint32_t cand_persistent;    /* candidates: 1 = fixed grid with reads handed out by an atomic
+                                  counter (uneven reads in one persistent launch) */
+  uint32_t cand_groups_per_cu; /* candidates, persistent: workgroups per CU in the fixed grid */
+  uint32_t n_tried;            /* grim_tune: shapes timed */
+  double best_ms;              /* grim_tune: kernel time of the chosen shape on the sample */
+  double default_ms;           /* grim_tune: kernel time of the default shape on the sample */
+} grim_tune_result;
+
+/* Time every launch shape of one mode on a sample read set and keep the
+ * fastest on `idx` for later calls (and in the file named by the
+ * GRIM_TUNE_CACHE environment variable, keyed by mode, q and size class, for
+ * later processes). Mode: candidates if cand_off is non-NULL (device arrays
+ * as in grim_filter_candidates), else all-bins. The sample should be large
+ * enough to fill the GPU. Errors: as the corresponding filter call. */
+int grim_tune(grim_index* idx, const grim_reads* sample, const int64_t* cand_off, const int32_t* cand_bin,
+              uint64_t n_cand, void* hip_stream, grim_tune_result* out);
+
+/* Read or set the launch shape used by `idx` for one mode (cfg->mode). */
+int grim_index_get_config(const grim_index* idx, uint32_t mode, grim_tune_result* out);
+int grim_index_set_config(grim_index* idx, const grim_tune_result* cfg);
+
+/* Batcher: a double-buffered, graph-captured loop over batches of reads held
+ * in pinned host memory. Each of its two slots owns pinned host buffers,
+ * device buffers, a stream and an instantiated hipGraph of the batch's
+ * kernels (status reset -> tokenize -> filter), launched between the
+ * batch's H2D and D2H copies on the slot's stream. Fill a slot's host
+ * buffers, submit, and wait; with two slots, one batch's copies overlap the
+ * other's kernels. The launch shape is the index's at
+ * creation time (tune first). Results: candidate counts/pass flags land in
+ * the slot's pinned host buffers; all-bins masks stay in the slot's device
+ * buffer (mask_out), mask_words uint32 per read. */
+typedef struct grim_batcher grim_batcher;
+
+#define GRIM_BATCH_EDITS_NONE 0u /* every read uses err_permille_all */
+#define GRIM_BATCH_EDITS_MAX 1u  /* `edits` holds E_r per read */
+#define GRIM_BATCH_EDITS_ERR 2u  /* `edits` holds e_r per read, per mille */
+
+typedef struct {
+  uint8_t* bases;      /* pinned host [max_bases] */
+  int64_t* offsets;    /* pinned host [max_reads + 1], offsets[0] = 0 */
+  uint16_t* edits;     /* pinned host [max_reads] per edits_kind, or NULL */
+  int64_t* cand_off;   /* pinned host [max_reads + 1] (candidates), from 0 to n_cand */
+  int32_t* cand_bin;   /* pinned host [max_cand] (candidates) */
+  uint16_t* count_out; /* pinned host [max_cand] (candidates): filled when the batch completes */
+  uint8_t* pass_out;   /* pinned host [max_cand] (candidates) */
+  uint32_t* mask_out;  /* device [max_reads][mask_words] (all-bins) */
+} grim_batch_buffers;
+
+/* Create a batcher for `mode` with the given capacities. Errors: GRIM_EINVAL,
+ * GRIM_ENOMEM, GRIM_EDEVICE. The index must outlive the batcher. */
+int grim_batcher_create(const grim_index* idx, uint32_t mode, uint64_t max_reads, uint64_t max_bases,
+                        uint64_t max_cand, uint32_t edits_kind, uint32_t err_permille_all, uint32_t flags,
+                        grim_batcher** out);
+
+/* Buffers of slot 0 or 1 (owned by the batcher). */
+int grim_batcher_buffers(grim_batcher* b, uint32_t slot, grim_batch_buffers* out);
+
+/* Launch the slot's graph on a batch of n_reads reads / n_bases bases /
+ * n_cand pairs already written to its host buffers. Returns at once; the
+ * host buffers must not change until grim_batcher_wait. */
+int grim_batcher_submit(grim_batcher* b, uint32_t slot, uint64_t n_reads, uint64_t n_bases, uint64_t n_cand);
+
+/* Wait for the slot's batch; returns its status (as the filter calls). */
+int grim_batcher_wait(grim_batcher* b, uint32_t slot);
+
+/* The HIP stream of a slot (for ordering device work on its mask_out). */
+void* grim_batcher_stream(grim_batcher* b, uint32_t slot);
+
+/* Free a batcher (waits for batches in flight; NULL is ignored). */
+void grim_batcher_free(grim_batcher* b);
+
 /* Kernel timing, recorded with HIP events on the stream each kernel runs on. */
 typedef struct {
   uint64_t launches;

@@ -209,6 +209,26 @@ int tokenize_reads(grim_index* idx, const grim_reads* rd, const ReadView& v, uin
   return GRIM_OK;
 }
 
+}  // namespace
+
+int prepare_reads(grim_index* idx, const grim_reads* rd, uint32_t max_tokens, uint32_t tok_shift, hipStream_t s,
+                  const int64_t** offsets_dev) {
+  int rc = check_reads_args(idx, rd);
+  if (rc) return rc;
+  ReadView v;
+  rc = stage_reads(idx, rd, s, &v);
+  if (rc) return rc;
+  ProfSpan pt(PROF_TOKENIZE);
+  rc = tokenize_reads(idx, rd, v, max_tokens, tok_shift, s, pt);
+  if (rc) return rc;
+  *offsets_dev = v.offsets;
+  return GRIM_OK;
+}
+
+void apply_cached_config(grim_index* idx, uint32_t mode, uint64_t n_reads, uint64_t n_bases, uint64_t n_cand);
+
+namespace {
+
 int finish_status(grim_index* idx, hipStream_t s) {
   grim_workspace& ws = idx->ws;
   GRIM_HIP_TRY(hipMemcpyAsync(ws.status_host, ws.status, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -216,14 +236,22 @@ int finish_status(grim_index* idx, hipStream_t s) {
   return status_to_error(ws.status_host[0]);
 }
 
-ScanConfig scan_config_from_env() {
-  ScanConfig c;
+ScanConfig scan_config_from_env(ScanConfig c) {
   if (const char* t = std::getenv("GRIM_SCAN_THREADS")) c.threads = std::atoi(t);
   if (const char* t = std::getenv("GRIM_SCAN_CHUNK")) c.reads_per_chunk = std::atoi(t);
   if (const char* t = std::getenv("GRIM_SCAN_LANE_WORDS")) c.lane_words = std::atoi(t);
   if (c.threads != 256 && c.threads != 512 && c.threads != 1024) c.threads = 1024;
   if (c.lane_words != 4 && c.lane_words != 8) c.lane_words = 4;
   if (c.reads_per_chunk < 64) c.reads_per_chunk = 64;
+  return c;
+}
+
+CandConfig cand_config_from_env(CandConfig c) {
+  if (const char* t = std::getenv("GRIM_CAND_WAVES")) c.waves = std::atoi(t);
+  if (const char* t = std::getenv("GRIM_CAND_PERSISTENT")) c.persistent = std::atoi(t) ? 1 : 0;
+  if (const char* t = std::getenv("GRIM_CAND_GROUPS_PER_CU")) c.groups_per_cu = std::atoi(t);
+  if (c.waves < 0 || c.waves > 8) c.waves = 0;
+  if (c.groups_per_cu < 1 || c.groups_per_cu > 64) c.groups_per_cu = 2;
   return c;
 }
 
@@ -504,6 +532,7 @@ int grim_filter_scan(const grim_index* cidx, const grim_reads* rd, uint32_t* mas
   if (rd->n_reads == 0) return GRIM_OK;
   std::lock_guard<std::mutex> lk(idx->mu);
   DeviceGuard dg(idx->device);
+  apply_cached_config(idx, GRIM_MODE_SCAN, rd->n_reads, rd->n_bases, 0);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   ReadView v;
   rc = stage_reads(idx, rd, s, &v);
@@ -530,7 +559,7 @@ int grim_filter_scan(const grim_index* cidx, const grim_reads* rd, uint32_t* mas
   a.status = idx->ws.status;
   ProfSpan ps(PROF_SCAN);
   ps.start(s);
-  GRIM_HIP_TRY(launch_scan_allbins(a, scan_config_from_env(), s));
+  GRIM_HIP_TRY(launch_scan_allbins(a, scan_config_from_env(idx->scan_cfg), s));
   ps.stop(s);
   rc = finish_status(idx, s);
   pt.collect();
@@ -551,6 +580,7 @@ int grim_filter_candidates(const grim_index* cidx, const grim_reads* rd, const i
   if (rd->n_reads == 0) return GRIM_OK;
   std::lock_guard<std::mutex> lk(idx->mu);
   DeviceGuard dg(idx->device);
+  apply_cached_config(idx, GRIM_MODE_CANDIDATES, rd->n_reads, rd->n_bases, n_cand);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   ReadView v;
   rc = stage_reads(idx, rd, s, &v);
@@ -574,9 +604,10 @@ int grim_filter_candidates(const grim_index* cidx, const grim_reads* rd, const i
   a.count_out = count_out;
   a.pass_out = pass_out;
   a.status = idx->ws.status;
+  a.work = idx->ws.status + 4;
   ProfSpan ps(PROF_CAND);
   ps.start(s);
-  GRIM_HIP_TRY(launch_scan_candidates(a, s));
+  GRIM_HIP_TRY(launch_scan_candidates(a, cand_config_from_env(idx->cand_cfg), s));
   ps.stop(s);
   rc = finish_status(idx, s);
   pt.collect();

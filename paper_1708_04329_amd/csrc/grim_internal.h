@@ -59,7 +59,15 @@ constexpr uint64_t kTmRowAlign = 64;  // token-major rows padded to 64 words
 // ---------------------------------------------------------------------------
 // Kernel argument blocks and launchers (one translation unit each).
 // ---------------------------------------------------------------------------
+// Optional device-resident sizes, so one captured launch serves batches of
+// any size up to the capture's maximum: dyn[0] = reads, dyn[1] = bases,
+// dyn[2] = candidate pairs.
+struct DynSizes {
+  uint64_t n_reads, n_bases, n_cand, pad;
+};
+
 struct TokArgs {
+  const DynSizes* dyn;  // overrides n_reads / n_bases when non-null
   const uint8_t* bases;
   const int64_t* offsets;
   uint64_t n_reads;
@@ -91,7 +99,18 @@ struct BuildArgs {
 hipError_t launch_build_tm(const BuildArgs& a, hipStream_t s);
 hipError_t launch_build_bm(const BuildArgs& a, hipStream_t s);
 
+// Per-read descriptor for scans over reads scattered across buffers (served
+// requests): token list, output row and threshold of one read.
+struct ReadDesc {
+  const uint32_t* tok;  // code << scan_token_shift(q), padded to 32 with the zero row
+  uint32_t* out;        // mask row: W words
+  uint32_t ntok;
+  int32_t T;
+};
+
 struct ScanArgs {
+  const DynSizes* dyn;         // overrides n_reads when non-null
+  const ReadDesc* desc;        // per-read descriptors instead of tokens/offsets/thr/mask_out
   const uint32_t* tm;
   uint64_t row_words;
   uint32_t R4;
@@ -124,6 +143,8 @@ inline uint32_t scan_token_shift(uint32_t q) {
 hipError_t launch_scan_allbins(const ScanArgs& a, const ScanConfig& cfg, hipStream_t s);
 
 struct CandArgs {
+  const DynSizes* dyn;         // overrides n_reads / n_cand when non-null
+  uint32_t* work;              // persistent mode: work[0] hands out reads to wavefronts
   const uint32_t* bm;
   uint32_t vec_words;
   uint32_t R4;
@@ -140,7 +161,14 @@ struct CandArgs {
   uint8_t* pass_out;
   uint32_t* status;
 };
-hipError_t launch_scan_candidates(const CandArgs& a, hipStream_t s);
+struct CandConfig {
+  int waves = 0;         // wavefronts per workgroup (0: by vector size)
+  int persistent = 0;    // 1: fixed grid, reads handed out by an atomic counter
+  int groups_per_cu = 2; // persistent grid size = 256 CUs x groups_per_cu
+};
+hipError_t launch_scan_candidates(const CandArgs& a, const CandConfig& cfg, hipStream_t s);
+// Zero `n` uint32 words with a kernel (graph-safe, unlike a memset node).
+hipError_t launch_zero_words(uint32_t* p, uint32_t n, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Profiling: HIP events around kernels, on the stream they run on.
@@ -177,6 +205,9 @@ struct grim_workspace {
 };
 
 struct grim_index {
+  grim::ScanConfig scan_cfg;   // launch shape of the all-bins scan (defaults or tuned)
+  grim::CandConfig cand_cfg;   // launch shape of candidate checks (defaults or tuned)
+  bool scan_tuned = false, cand_tuned = false;
   int device = 0;
   uint64_t G = 0;
   uint32_t B = 0, O = 0, q = 0, layout = 0;

@@ -147,8 +147,9 @@ __device__ __forceinline__ uint32_t ge_threshold(const uint32_t (&pl)[NP], const
 }
 
 template <int LW, int NHI>
-__device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lane, bool active, uint64_t rid,
-                                          uint32_t ntok, uint64_t tbase, int32_t T, uint64_t gw0) {
+__device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lane, bool active,
+                                          const uint32_t* tok, uint32_t* out_row, uint64_t rid, uint32_t ntok,
+                                          int32_t T, uint64_t gw0) {
   constexpr int NP = 5 + NHI;
   Counters<LW, NHI> c;
 #pragma unroll
@@ -156,7 +157,7 @@ __device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lan
 #pragma unroll
     for (int j = 0; j < LW; ++j) c.p[k][j] = 0;
   const uint32_t nblk = active ? (ntok + 31) >> 5 : 0;
-  const uint4* tk4 = reinterpret_cast<const uint4*>(a.tokens + tbase);
+  const uint4* tk4 = reinterpret_cast<const uint4*>(tok);
   for (uint32_t b = 0; b < nblk; ++b) {
     uint32_t tk[32];
 #pragma unroll
@@ -182,7 +183,7 @@ __device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lan
     for (int k = 0; k < NP; ++k) pl[k] = c.p[k][j];
     uint32_t ge = ge_threshold<NP>(pl, km, allpass);
     if (gw == a.W - 1 && (a.nb & 31)) ge &= (1u << (a.nb & 31)) - 1u;
-    a.mask_out[rid * a.W + gw] = ge;
+    out_row[gw] = ge;
     if (a.counts_out) {
       const uint64_t xb = gw * 32;
       for (int b = 0; b < 32; ++b) {
@@ -212,7 +213,9 @@ __global__ __launch_bounds__(NT) void k_scan_allbins(ScanArgs a) {
   const uint32_t tile = slot - rc_local * a.n_tiles;
   const uint32_t rchunk = rc_local * 8u + xcd;
   if (rchunk >= a.n_rchunks) return;
-  if (a.status[0] != 0) return;  // inputs were rejected: leave outputs untouched
+  const uint64_t n_reads = a.dyn ? min(a.dyn->n_reads, a.n_reads) : a.n_reads;
+  if ((uint64_t)rchunk * a.reads_per_chunk >= n_reads) return;
+  if (a.status && a.status[0] != 0) return;  // inputs were rejected: leave outputs untouched
 
   // stage the tile: rows 0..R4-1 from HBM, row R4 = zeros
   const uint32_t R4 = a.R4;
@@ -241,23 +244,34 @@ __global__ __launch_bounds__(NT) void k_scan_allbins(ScanArgs a) {
   const uint64_t gw0 = (uint64_t)tile * TW + (uint64_t)s * LW;
   const uint64_t r_begin = (uint64_t)rchunk * a.reads_per_chunk;
   uint64_t r_end = r_begin + a.reads_per_chunk;
-  if (r_end > a.n_reads) r_end = a.n_reads;
+  if (r_end > n_reads) r_end = n_reads;
 
   for (uint64_t base = r_begin + (uint64_t)wave * RPW; base < r_end; base += (uint64_t)NW * RPW) {
     const uint64_t k = base + g;
     const bool active = k < r_end;
-    uint64_t rid = 0, tbase = 0;
+    uint64_t rid = 0;
+    const uint32_t* tok = nullptr;
+    uint32_t* out_row = nullptr;
     uint32_t ntok = 0;
     int32_t T = 0;
     if (active) {
       rid = a.read_order ? a.read_order[k] : k;
-      const int64_t o0 = a.offsets[rid], o1 = a.offsets[rid + 1];
-      ntok = (uint32_t)(o1 - o0 - a.q + 1);
-      tbase = token_base(o0, rid);
-      T = a.thr[rid];
+      if (a.desc) {
+        const ReadDesc d = a.desc[rid];
+        tok = d.tok;
+        out_row = d.out;
+        ntok = d.ntok;
+        T = d.T;
+      } else {
+        const int64_t o0 = a.offsets[rid], o1 = a.offsets[rid + 1];
+        ntok = (uint32_t)(o1 - o0 - a.q + 1);
+        tok = a.tokens + token_base(o0, rid);
+        out_row = a.mask_out + rid * a.W;
+        T = a.thr[rid];
+      }
     }
-    if (__any(ntok > 255)) scan_read<LW, 11>(a, lds_lane, active, rid, ntok, tbase, T, gw0);
-    else scan_read<LW, 3>(a, lds_lane, active, rid, ntok, tbase, T, gw0);
+    if (__any(ntok > 255)) scan_read<LW, 11>(a, lds_lane, active, tok, out_row, rid, ntok, T, gw0);
+    else scan_read<LW, 3>(a, lds_lane, active, tok, out_row, rid, ntok, T, gw0);
   }
 }
 

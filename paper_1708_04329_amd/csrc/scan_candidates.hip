@@ -11,6 +11,11 @@
 // 16-byte loads and ANDs it with the planes (read from LDS with a
 // wave-uniform address, i.e. a broadcast), counting with v_bcnt. The gather
 // of one bin vector per pair is the compulsory traffic of this mode.
+//
+// Two launch shapes: one wavefront per read (the hardware dispatcher
+// balances), or a persistent grid whose wavefronts take the next read from an
+// atomic counter until none are left (reads of uneven length and candidate
+// count in one launch, no per-workgroup dispatch cost).
 
 #include "grim_internal.h"
 
@@ -25,19 +30,12 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int VW, int NW>
-__global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
-  constexpr uint32_t kHistWords = VW * 16;          // R4 / 2 packed uint16 counters (R4 = 32*VW)
-  constexpr uint32_t kPerWave = kHistWords + kMaxPlanes * VW;
-  __shared__ __attribute__((aligned(16))) uint32_t lds[NW * kPerWave];
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-  uint32_t* hist = lds + wave * kPerWave;
-  uint32_t* planes = hist + kHistWords;
-  const uint64_t r = (uint64_t)blockIdx.x * NW + wave;
-  if (r >= a.n_reads) return;
-  if (a.status[0] & ~(uint32_t)(ST_BAD_BIN | ST_BAD_CAND_OFF)) return;  // rejected reads
+template <int VW>
+__device__ __forceinline__ void cand_read(const CandArgs& a, uint64_t r, uint64_t n_cand, uint32_t* hist,
+                                          uint32_t* planes, uint32_t lane) {
+  constexpr uint32_t kHistWords = VW * 16;  // R4 / 2 packed uint16 counters (R4 = 32*VW)
   const int64_t c0 = a.cand_off[r], c1 = a.cand_off[r + 1];
-  if (c0 < 0 || c1 < c0 || (uint64_t)c1 > a.n_cand) {
+  if (c0 < 0 || c1 < c0 || (uint64_t)c1 > n_cand) {
     if (lane == 0) atomicOr(a.status, ST_BAD_CAND_OFF);
     return;
   }
@@ -124,27 +122,86 @@ __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
     if (a.count_out) a.count_out[c] = (uint16_t)cnt;
     if (a.pass_out) a.pass_out[c] = (int32_t)cnt >= T ? 1 : 0;
   }
+  // the LDS of this wavefront is reused by its next read
+  wave_sync();
 }
 
-template <int VW>
-hipError_t launch_vw(const CandArgs& a, hipStream_t s) {
-  constexpr int NW = VW >= 512 ? 1 : (VW >= 128 ? 4 : 8);
-  const uint64_t blocks = (a.n_reads + NW - 1) / NW;
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_scan_cand<VW, NW>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, a);
+template <int VW, int NW, bool PERSISTENT>
+__global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
+  constexpr uint32_t kHistWords = VW * 16;
+  constexpr uint32_t kPerWave = kHistWords + kMaxPlanes * VW;
+  __shared__ __attribute__((aligned(16))) uint32_t lds[NW * kPerWave];
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  uint32_t* hist = lds + wave * kPerWave;
+  uint32_t* planes = hist + kHistWords;
+  const uint64_t n_reads = a.dyn ? min(a.dyn->n_reads, a.n_reads) : a.n_reads;
+  const uint64_t n_cand = a.dyn ? min(a.dyn->n_cand, a.n_cand) : a.n_cand;
+  if (a.status[0] & ~(uint32_t)(ST_BAD_BIN | ST_BAD_CAND_OFF)) return;  // rejected reads
+  if constexpr (!PERSISTENT) {
+    const uint64_t r = (uint64_t)blockIdx.x * NW + wave;
+    if (r < n_reads) cand_read<VW>(a, r, n_cand, hist, planes, lane);
+  } else {
+    // every wavefront leaves once the counter has passed n_reads
+    while (true) {
+      uint32_t r = 0;
+      if (lane == 0) r = atomicAdd(a.work, 1u);
+      r = __shfl(r, 0);
+      if ((uint64_t)r >= n_reads) break;
+      cand_read<VW>(a, r, n_cand, hist, planes, lane);
+    }
+  }
+}
+
+template <int VW, int NW>
+hipError_t launch_nw(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
+  if (cfg.persistent) {
+    if (!a.work) return hipErrorInvalidValue;
+    const uint64_t blocks = 256ull * (uint64_t)max(1, cfg.groups_per_cu);
+    hipError_t e = launch_zero_words(a.work, 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_scan_cand<VW, NW, true>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, a);
+  } else {
+    const uint64_t blocks = (a.n_reads + NW - 1) / NW;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_scan_cand<VW, NW, false>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, a);
+  }
   return hipGetLastError();
+}
+
+// LDS per wavefront: (16 + kMaxPlanes) * VW words; the wave count per group
+// is capped so a group stays within 64 KB.
+template <int VW>
+hipError_t launch_vw(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
+  constexpr int kMaxNW = VW >= 512 ? 1 : (VW >= 128 ? 4 : 8);
+  const int nw = cfg.waves > 0 ? cfg.waves : kMaxNW;
+  if (nw >= 8 && kMaxNW >= 8) return launch_nw<VW, (kMaxNW >= 8 ? 8 : 1)>(a, cfg, s);
+  if (nw >= 4 && kMaxNW >= 4) return launch_nw<VW, (kMaxNW >= 4 ? 4 : 1)>(a, cfg, s);
+  if (nw >= 2 && kMaxNW >= 2) return launch_nw<VW, (kMaxNW >= 2 ? 2 : 1)>(a, cfg, s);
+  return launch_nw<VW, 1>(a, cfg, s);
+}
+
+__global__ void k_zero_words(uint32_t* p, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 }  // namespace
 
-hipError_t launch_scan_candidates(const CandArgs& a, hipStream_t s) {
+hipError_t launch_zero_words(uint32_t* p, uint32_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_words, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_candidates(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
+  if (a.n_reads == 0) return hipSuccess;
   switch (a.vec_words) {
-    case 1: return launch_vw<1>(a, s);
-    case 2: return launch_vw<2>(a, s);
-    case 8: return launch_vw<8>(a, s);
-    case 32: return launch_vw<32>(a, s);
-    case 128: return launch_vw<128>(a, s);
-    case 512: return launch_vw<512>(a, s);
+    case 1: return launch_vw<1>(a, cfg, s);
+    case 2: return launch_vw<2>(a, cfg, s);
+    case 8: return launch_vw<8>(a, cfg, s);
+    case 32: return launch_vw<32>(a, cfg, s);
+    case 128: return launch_vw<128>(a, cfg, s);
+    case 512: return launch_vw<512>(a, cfg, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -31,11 +31,13 @@ __device__ __forceinline__ int base_code(uint32_t b) {
 __global__ __launch_bounds__(256) void k_tokenize(TokArgs a) {
   const uint64_t r = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
   const uint32_t lane = threadIdx.x & 63u;
-  if (r >= a.n_reads) return;
+  const uint64_t n_reads = a.dyn ? min(a.dyn->n_reads, a.n_reads) : a.n_reads;
+  const uint64_t n_bases = a.dyn ? min(a.dyn->n_bases, a.n_bases) : a.n_bases;
+  if (r >= n_reads) return;
   const int64_t o0 = a.offsets[r], o1 = a.offsets[r + 1];
   uint32_t err = 0;
   int64_t L = o1 - o0;
-  if (o0 < 0 || o1 < o0 || (uint64_t)o1 > a.n_bases) { err |= ST_BAD_LENGTH; L = 0; }
+  if (o0 < 0 || o1 < o0 || (uint64_t)o1 > n_bases) { err |= ST_BAD_LENGTH; L = 0; }
   const uint32_t q = a.q;
   if (L < (int64_t)q) err |= ST_BAD_LENGTH;
   const int64_t ntok = L >= (int64_t)q ? L - q + 1 : 0;
@@ -78,6 +80,7 @@ __global__ __launch_bounds__(256) void k_tokenize(TokArgs a) {
 
 }  // namespace
 
+// With a.dyn set, a.n_reads / a.n_bases are the capacities the grid is sized for.
 hipError_t launch_tokenize(const TokArgs& a, hipStream_t s) {
   if (a.n_reads == 0) return hipSuccess;
   const uint64_t blocks = (a.n_reads + 3) / 4;

@@ -32,6 +32,11 @@ GRIM_EIO = -8
 LAYOUT_TM = 1
 LAYOUT_BM = 2
 READS_ALLOW_SHORT_OVERLAP = 1
+MODE_SCAN = 1
+MODE_CANDIDATES = 2
+BATCH_EDITS_NONE = 0
+BATCH_EDITS_MAX = 1
+BATCH_EDITS_ERR = 2
 
 _NAMES = {0: "GRIM_OK", -1: "GRIM_EINVAL", -2: "GRIM_ENOMEM", -3: "GRIM_EDEVICE", -4: "GRIM_EOVERLAP",
           -5: "GRIM_EAGAIN", -6: "GRIM_ETIMEDOUT", -7: "GRIM_ECANCELED", -8: "GRIM_EIO"}
@@ -61,6 +66,22 @@ class _Reads(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_uint32), ("threads", ctypes.c_uint32), ("reads_per_chunk", ctypes.c_uint32),
+                ("lane_words", ctypes.c_uint32), ("cand_waves", ctypes.c_uint32), ("cand_persistent", ctypes.c_uint32),
+                ("cand_groups_per_cu", ctypes.c_uint32), ("n_tried", ctypes.c_uint32), ("best_ms", ctypes.c_double),
+                ("default_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchBuffers(ctypes.Structure):
+    _fields_ = [("bases", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("edits", ctypes.c_void_p),
+                ("cand_off", ctypes.c_void_p), ("cand_bin", ctypes.c_void_p), ("count_out", ctypes.c_void_p),
+                ("pass_out", ctypes.c_void_p), ("mask_out", ctypes.c_void_p)]
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double), ("last_ms", ctypes.c_double)]
 
@@ -71,7 +92,9 @@ class Profile(ctypes.Structure):
 
 EXPORTS = ["grim_abi_version", "grim_last_error", "grim_build_index", "grim_index_info", "grim_index_read",
            "grim_index_save", "grim_index_load", "grim_index_free", "grim_filter_scan", "grim_filter_candidates",
-           "grim_profile_enable", "grim_profile_read"]
+           "grim_profile_enable", "grim_profile_read", "grim_tune", "grim_index_get_config",
+           "grim_index_set_config", "grim_batcher_create", "grim_batcher_buffers", "grim_batcher_submit",
+           "grim_batcher_wait", "grim_batcher_stream", "grim_batcher_free"]
 
 _lib = None
 
@@ -99,6 +122,15 @@ def lib(path: str = LIB_PATH):
         "grim_filter_candidates": ([P, ctypes.POINTER(_Reads), P, P, U64, P, P, P], I),
         "grim_profile_enable": ([I], I),
         "grim_profile_read": ([ctypes.POINTER(Profile), I], I),
+        "grim_tune": ([P, ctypes.POINTER(_Reads), P, P, U64, P, ctypes.POINTER(TuneResult)], I),
+        "grim_index_get_config": ([P, U32, ctypes.POINTER(TuneResult)], I),
+        "grim_index_set_config": ([P, ctypes.POINTER(TuneResult)], I),
+        "grim_batcher_create": ([P, U32, U64, U64, U64, U32, U32, U32, PP], I),
+        "grim_batcher_buffers": ([P, U32, ctypes.POINTER(BatchBuffers)], I),
+        "grim_batcher_submit": ([P, U32, U64, U64, U64], I),
+        "grim_batcher_wait": ([P, U32], I),
+        "grim_batcher_stream": ([P, U32], P),
+        "grim_batcher_free": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -298,3 +330,88 @@ def grim_profile_read(reset: bool = False) -> dict:
 
 def grim_abi_version() -> int:
     return lib().grim_abi_version()
+
+
+# ---------------------------------------------------------------------------
+# batching layer
+# ---------------------------------------------------------------------------
+
+def grim_tune(index: Index, sample: ReadSet, cand_off=None, cand_bin=None, stream=None) -> dict:
+    """Time the launch shapes of one mode on ``sample`` and keep the fastest on ``index``."""
+    out = TuneResult()
+    r = sample._struct()
+    n_cand = 0 if cand_bin is None else len(cand_bin)
+    _check(lib().grim_tune(index.handle, ctypes.byref(r), _ptr(cand_off), _ptr(cand_bin), n_cand,
+                           _stream_handle(stream), ctypes.byref(out)))
+    return out.as_dict()
+
+
+def grim_index_get_config(index: Index, mode: int) -> dict:
+    out = TuneResult()
+    _check(lib().grim_index_get_config(index.handle, mode, ctypes.byref(out)))
+    return out.as_dict()
+
+
+def grim_index_set_config(index: Index, cfg: dict):
+    t = TuneResult()
+    for k, v in cfg.items():
+        setattr(t, k, v)
+    _check(lib().grim_index_set_config(index.handle, ctypes.byref(t)))
+
+
+class Batcher:
+    """Double-buffered, graph-captured batch loop (see grim_batcher_* in grim.h).
+
+    ``buffers(slot)`` returns numpy views of the slot's pinned host buffers
+    (and the device address of its all-bins mask buffer)."""
+
+    def __init__(self, index: Index, mode: int, max_reads: int, max_bases: int, max_cand: int = 0,
+                 edits_kind: int = BATCH_EDITS_NONE, err_permille_all: int = 0, allow_short_overlap: bool = False):
+        self.index = index  # keeps the index alive
+        self.mode = mode
+        self.max_reads, self.max_bases, self.max_cand = max_reads, max_bases, max_cand
+        self.edits_kind = edits_kind
+        h = ctypes.c_void_p()
+        _check(lib().grim_batcher_create(index.handle, mode, max_reads, max_bases, max_cand, edits_kind,
+                                         err_permille_all, READS_ALLOW_SHORT_OVERLAP if allow_short_overlap else 0,
+                                         ctypes.byref(h)))
+        self._h = h
+
+    def buffers(self, slot: int) -> dict:
+        b = BatchBuffers()
+        _check(lib().grim_batcher_buffers(self._h, slot, ctypes.byref(b)))
+
+        def view(ptr, ctype, n):
+            if not ptr:
+                return None
+            return np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ctype)), shape=(n,))
+
+        out = {"bases": view(b.bases, ctypes.c_uint8, self.max_bases),
+               "offsets": view(b.offsets, ctypes.c_int64, self.max_reads + 1),
+               "edits": view(b.edits, ctypes.c_uint16, self.max_reads),
+               "cand_off": view(b.cand_off, ctypes.c_int64, self.max_reads + 1),
+               "cand_bin": view(b.cand_bin, ctypes.c_int32, max(self.max_cand, 1)),
+               "count_out": view(b.count_out, ctypes.c_uint16, max(self.max_cand, 1)),
+               "pass_out": view(b.pass_out, ctypes.c_uint8, max(self.max_cand, 1)),
+               "mask_out_device": b.mask_out}
+        return out
+
+    def submit(self, slot: int, n_reads: int, n_bases: int, n_cand: int = 0):
+        _check(lib().grim_batcher_submit(self._h, slot, n_reads, n_bases, n_cand))
+
+    def wait(self, slot: int):
+        _check(lib().grim_batcher_wait(self._h, slot))
+
+    def stream(self, slot: int) -> int:
+        return lib().grim_batcher_stream(self._h, slot)
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib().grim_batcher_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -125,3 +125,19 @@ def test_readset_marshalling_checks_dtypes():
                       max_edits=np.array([1], np.uint16), err_permille_all=50)
     s = rs._struct()
     assert s.n_reads == 1 and s.n_bases == 10 and s.on_device == 0 and s.err_permille_all == 50
+
+
+def test_batching_entry_points_reject_null_arguments():
+    L = grim.lib()
+    h = ctypes.c_void_p()
+    assert L.grim_batcher_create(None, 1, 10, 10, 0, 0, 0, 0, ctypes.byref(h)) == grim.GRIM_EINVAL
+    assert L.grim_batcher_submit(None, 0, 1, 1, 0) == grim.GRIM_EINVAL
+    assert L.grim_batcher_wait(None, 0) == grim.GRIM_EINVAL
+    assert L.grim_batcher_buffers(None, 0, None) == grim.GRIM_EINVAL
+    assert L.grim_batcher_stream(None, 0) is None
+    L.grim_batcher_free(None)
+    r = grim._Reads()
+    t = grim.TuneResult()
+    assert L.grim_tune(None, ctypes.byref(r), None, None, 0, None, ctypes.byref(t)) == grim.GRIM_EINVAL
+    assert L.grim_index_get_config(None, 1, ctypes.byref(t)) == grim.GRIM_EINVAL
+    assert L.grim_index_set_config(None, ctypes.byref(t)) == grim.GRIM_EINVAL
