@@ -69,7 +69,10 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
+    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
+    p.add_argument("--serve-seconds", type=float, default=10.0,
+                   help="all-bins workloads: also replay this many seconds of the Poisson request stream through "
+                        "the continuous and the plain server (0 = skip; the serving workload uses 60)")
     p.add_argument("--reads-scale", type=float, default=1.0, help="fraction of the stated read count (testing only)")
     p.add_argument("--genome-len", type=int, default=0, help="override genome length (testing only)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -98,6 +101,13 @@ def main():
     if args.genome_len:
         w = C.shrink(w, genome_len=args.genome_len)
 
+    if args.workload == "c5":
+        # the serving workload runs on the human-scale index; its step is the request stream
+        w = C.workload("c3")
+        if args.genome_len:
+            w = C.shrink(w, genome_len=args.genome_len)
+        if args.serve_seconds == 10.0:
+            args.serve_seconds = 60.0
     t0 = time.time()
     ref = synth.genome(w.genome)
     log(f"genome {len(ref):,} bp in {time.time() - t0:.1f}s")
@@ -221,7 +231,133 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, w, ref, rd, me, ep, idx, info, cand, mask if w.mode == "allbins"
                                            else (cnt, pas))
+    if w.mode == "allbins" and args.serve_seconds > 0:
+        del mask
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out["serving"] = serving(args, ref, idx, info)
+        if args.workload == "c5":
+            sv = out["serving"]
+            out["config"]["workload"] = "c5_serving_3.1Gbp_q5"
+            out["metric_parts"] = {"served_reads_per_s": sv["continuous"]["reads_per_s"],
+                                   "p99_ms": sv["continuous"]["p99_ms"],
+                                   "plain_reads_per_s": sv["plain"]["reads_per_s"],
+                                   "plain_p99_ms": sv["plain"]["p99_ms"]}
     print(json.dumps(out), flush=True)
+
+
+def request_stream(seconds: float, rate: float, pool_n: int, seed: int, size_max: int = 20000):
+    """Poisson arrivals (exponential gaps at `rate`/s) of log-uniform sizes in [1, size_max],
+    each a contiguous slice of the read pool; drawn with SplitMix64."""
+    import math
+    import synth
+    g = synth.SplitMix64(seed)
+    t, out = 0.0, []
+    while True:
+        t += -math.log(1.0 - g.uniform()) / rate
+        if t >= seconds:
+            break
+        n = min(size_max, max(1, int(math.exp(g.uniform() * math.log(size_max + 1)))))
+        start = int(g.uniform() * (pool_n - n + 1))
+        out.append((t, start, n))
+    return out
+
+
+def serving(args, ref, idx, info):
+    """Replay one seeded request stream through the continuous and the plain server."""
+    import ctypes
+    import threading
+    import synth
+    import synth.configs as C
+    from paper_1708_04329_amd import grim
+    w5 = C.workload("c5")
+    pool_n = 400_000
+    spec = w5.reads
+    spec.n_reads = pool_n
+    t0 = time.time()
+    pool = synth.reads(spec, ref)
+    stream = request_stream(args.serve_seconds, 200.0, pool_n, seed=w5.reads.seed + 17)
+    reqs = []
+    for (ta, start, n) in stream:
+        o0 = int(pool.offsets[start])
+        offs = (pool.offsets[start:start + n + 1] - o0).astype(np.int64)
+        bases = pool.bases[o0:o0 + int(offs[-1])]
+        reqs.append((ta, grim.ReadSet(bases, np.ascontiguousarray(offs),
+                                      err_permille=np.ascontiguousarray(pool.err_pm[start:start + n].astype(np.uint16))),
+                     start, n))
+    offered = sum(r[3] for r in reqs) / args.serve_seconds
+    log(f"serving: {len(reqs)} requests over {args.serve_seconds:.0f}s, {offered:,.0f} reads/s offered "
+        f"(pool built in {time.time() - t0:.1f}s)")
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    W = info["mask_words"]
+    results = {}
+    for name, policy in (("continuous", grim.SERVE_CONTINUOUS), ("plain", grim.SERVE_PLAIN)):
+        srv = grim.Server(idx, policy, reserve_bytes=8 << 30, max_inflight=256, max_request_reads=20000)
+        tickets = [None] * len(reqs)
+        small = [i for i, r in enumerate(reqs) if r[3] <= 2000]
+        check_ids = set(small[::max(1, len(small) // 8)][:8])
+        exact = [True]
+        done_evt = threading.Event()
+
+        def collector():
+            for i in range(len(reqs)):
+                while tickets[i] is None:
+                    time.sleep(0.0005)
+                res = srv.wait(tickets[i], -1)
+                if res["status"] != grim.GRIM_OK:
+                    exact[0] = False
+                elif i in check_ids:
+                    n = reqs[i][3]
+                    got = np.empty(n * W, np.uint32)
+                    hip.hipMemcpy(got.ctypes.data, res["mask"], n * W * 4, 2)
+                    results.setdefault("_checks", []).append((i, got))
+                srv.release(tickets[i])
+            done_evt.set()
+
+        th = threading.Thread(target=collector)
+        th.start()
+        start = time.perf_counter()
+        for i, (ta, rs, _, _) in enumerate(reqs):
+            delay = ta - (time.perf_counter() - start)
+            if delay > 0:
+                time.sleep(delay)
+            while True:
+                try:
+                    tickets[i] = srv.submit(rs)
+                    break
+                except grim.GrimError as e:
+                    if e.code != grim.GRIM_EAGAIN:
+                        raise
+                    time.sleep(0.001)
+        done_evt.wait()
+        th.join()
+        st = srv.stats()
+        srv.destroy()
+        checks = results.pop("_checks", [])
+        # bit-exact against the one-shot call on the same reads alone
+        import torch
+        for i, got in checks:
+            rs = reqs[i][1]
+            m = torch.empty((reqs[i][3], W), dtype=torch.uint32, device="cuda")
+            grim.grim_filter_scan(idx, grim.ReadSet(torch.from_numpy(rs.bases).cuda(),
+                                                    torch.from_numpy(rs.offsets).cuda(),
+                                                    err_permille=torch.from_numpy(rs.err_permille).cuda()), m)
+            if not np.array_equal(m.cpu().numpy().reshape(-1), got):
+                exact[0] = False
+            del m
+        results[name] = {"requests": st["completed"], "failed": st["failed"], "launches": st["launches"],
+                         "reads_per_s": st["reads_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                         "max_ms": st["max_ms"], "mean_ms": st["mean_ms"],
+                         "peak_device_gb": st["peak_device_bytes"] / 1e9,
+                         "sampled_requests_bit_exact": exact[0] and st["failed"] == 0}
+        log(f"serving {name}: {st['reads_per_s']:,.0f} reads/s, p50 {st['p50_ms']:.2f} ms, "
+            f"p99 {st['p99_ms']:.2f} ms, {st['launches']} launches, exact {exact[0]}")
+    results["offered_reads_per_s"] = offered
+    results["requests"] = len(reqs)
+    results["seconds"] = args.serve_seconds
+    results["arrivals"] = "Poisson 200 req/s, log-uniform 1..20000 reads of 100/150/250 bp (30/40/30), e in 2..5%"
+    return results
 
 
 def cpu_baseline(args, w, ref, rd, me, ep, idx, info, cand, gpu_out):

@@ -258,6 +258,98 @@ void* grim_batcher_stream(grim_batcher* b, uint32_t slot);
 /* Free a batcher (waits for batches in flight; NULL is ignored). */
 void grim_batcher_free(grim_batcher* b);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of all-bins scans against a resident index.
+ * Requests (read sets in host memory) are copied at submit, admitted in
+ * arrival order while fewer than max_inflight are admitted and their device
+ * footprint (inputs, tokens, thresholds, descriptors and their pass masks)
+ * fits the free bytes of the server's device arena, a block of HBM taken at
+ * creation (by default all free HBM minus reserve_bytes). The continuous
+ * policy lets requests that arrive while others run join the next launch:
+ * every launch takes up to max_batch_reads reads from the admitted requests,
+ * at most slice_reads from each, and launches are spread over n_streams
+ * streams. The plain policy runs each request alone as one launch, in arrival
+ * order, on one stream (the one-launch-per-batch form, for comparison).
+ * A request's pass masks are the same bits grim_filter_scan computes for its
+ * reads alone; they stay in device memory until grim_serve_release.
+ * ---------------------------------------------------------------------- */
+typedef struct grim_server grim_server;
+
+#define GRIM_SERVE_CONTINUOUS 0u
+#define GRIM_SERVE_PLAIN 1u
+
+typedef struct {
+  uint32_t policy;            /* GRIM_SERVE_CONTINUOUS or GRIM_SERVE_PLAIN */
+  uint32_t max_inflight;      /* admitted requests at once (0: 64) */
+  uint32_t max_batch_reads;   /* reads per launch, continuous policy (0: 16384) */
+  uint32_t slice_reads;       /* reads one request adds to a launch (0: 4096) */
+  uint32_t n_streams;         /* device streams for launches (0: 4; plain: 1) */
+  uint32_t max_request_reads; /* largest request accepted (0: 65536) */
+  uint64_t arena_bytes;       /* device bytes the server serves from (0: free HBM - reserve_bytes) */
+  uint64_t reserve_bytes;     /* HBM left free when arena_bytes = 0 */
+  uint64_t host_arena_bytes;  /* pinned host bytes for submitted reads (0: 1 GiB) */
+  uint32_t flags;             /* GRIM_READS_* for every request */
+  uint32_t reserved;
+} grim_serve_config;
+
+typedef struct {
+  uint64_t ticket;
+  int32_t status;        /* GRIM_OK, or the request's error (GRIM_EINVAL, GRIM_EOVERLAP,
+                            GRIM_ECANCELED, GRIM_EDEVICE) */
+  uint32_t reserved;
+  uint64_t n_reads;
+  uint64_t mask_words;
+  const uint32_t* mask;  /* device [n_reads][mask_words] when status is GRIM_OK; valid until
+                            grim_serve_release */
+  double latency_ms;     /* submit -> completion observed by the server */
+  double queue_ms;       /* submit -> admitted */
+} grim_result;
+
+typedef struct {
+  uint64_t submitted, completed, failed, rejected, canceled;
+  uint64_t reads_completed;
+  uint64_t launches;          /* scan launches made */
+  uint64_t peak_device_bytes; /* high-water mark of the arena in use */
+  uint64_t arena_bytes;
+  double p50_ms, p99_ms, max_ms, mean_ms; /* latency of completed requests (nearest rank) */
+  double reads_per_s;         /* completed reads / (last completion - first submit) */
+  uint32_t queued, admitted;
+} grim_serve_stats_t;
+
+/* Start a server over `idx` (token-major layout) with a scheduler thread.
+ * cfg may be NULL for defaults. The index must outlive the server.
+ * Errors: GRIM_EINVAL, GRIM_ENOMEM (arena), GRIM_EDEVICE. */
+int grim_serve_create(const grim_index* idx, const grim_serve_config* cfg, grim_server** out);
+
+/* Queue a request; its reads (host memory, on_device = 0, offsets from 0 to
+ * n_bases, flags = 0) are copied before the call returns. Errors:
+ * GRIM_EINVAL, GRIM_ENOMEM (the request's footprint exceeds the whole arena,
+ * so it could never be admitted), GRIM_EAGAIN (host staging full: retry after
+ * completions). */
+int grim_serve_submit(grim_server* s, const grim_reads* reads, uint64_t* ticket);
+
+/* Result of a request if it has ended (returns its status), else GRIM_EAGAIN. */
+int grim_serve_poll(grim_server* s, uint64_t ticket, grim_result* out);
+
+/* Wait up to timeout_ms (< 0: no limit) for a request to end; returns its
+ * status, or GRIM_ETIMEDOUT. */
+int grim_serve_wait(grim_server* s, uint64_t ticket, int timeout_ms, grim_result* out);
+
+/* Give an ended request's device memory back to the arena and forget it. */
+int grim_serve_release(grim_server* s, uint64_t ticket);
+
+/* Cancel a request: queued ones end at once, admitted ones once their
+ * launches in flight finish (status GRIM_ECANCELED). */
+int grim_serve_cancel(grim_server* s, uint64_t ticket);
+
+/* Counters and latency statistics since creation or the last reset. */
+int grim_serve_stats(grim_server* s, grim_serve_stats_t* out);
+int grim_serve_reset_stats(grim_server* s);
+
+/* Stop: queued requests are cancelled, admitted ones drain, then all device
+ * and host memory of the server is freed (NULL is ignored). */
+void grim_serve_destroy(grim_server* s);
+
 /* Kernel timing, recorded with HIP events on the stream each kernel runs on. */
 typedef struct {
   uint64_t launches;

@@ -82,6 +82,35 @@ class BatchBuffers(ctypes.Structure):
                 ("pass_out", ctypes.c_void_p), ("mask_out", ctypes.c_void_p)]
 
 
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("policy", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32), ("max_batch_reads", ctypes.c_uint32),
+                ("slice_reads", ctypes.c_uint32), ("n_streams", ctypes.c_uint32),
+                ("max_request_reads", ctypes.c_uint32), ("arena_bytes", ctypes.c_uint64),
+                ("reserve_bytes", ctypes.c_uint64), ("host_arena_bytes", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32), ("reserved", ctypes.c_uint32),
+                ("n_reads", ctypes.c_uint64), ("mask_words", ctypes.c_uint64), ("mask", ctypes.c_void_p),
+                ("latency_ms", ctypes.c_double), ("queue_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("canceled", ctypes.c_uint64), ("reads_completed", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("peak_device_bytes", ctypes.c_uint64),
+                ("arena_bytes", ctypes.c_uint64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("mean_ms", ctypes.c_double), ("reads_per_s", ctypes.c_double),
+                ("queued", ctypes.c_uint32), ("admitted", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double), ("last_ms", ctypes.c_double)]
 
@@ -94,7 +123,9 @@ EXPORTS = ["grim_abi_version", "grim_last_error", "grim_build_index", "grim_inde
            "grim_index_save", "grim_index_load", "grim_index_free", "grim_filter_scan", "grim_filter_candidates",
            "grim_profile_enable", "grim_profile_read", "grim_tune", "grim_index_get_config",
            "grim_index_set_config", "grim_batcher_create", "grim_batcher_buffers", "grim_batcher_submit",
-           "grim_batcher_wait", "grim_batcher_stream", "grim_batcher_free"]
+           "grim_batcher_wait", "grim_batcher_stream", "grim_batcher_free", "grim_serve_create",
+           "grim_serve_submit", "grim_serve_poll", "grim_serve_wait", "grim_serve_release", "grim_serve_cancel",
+           "grim_serve_stats", "grim_serve_reset_stats", "grim_serve_destroy"]
 
 _lib = None
 
@@ -131,6 +162,15 @@ def lib(path: str = LIB_PATH):
         "grim_batcher_wait": ([P, U32], I),
         "grim_batcher_stream": ([P, U32], P),
         "grim_batcher_free": ([P], None),
+        "grim_serve_create": ([P, ctypes.POINTER(ServeConfig), PP], I),
+        "grim_serve_submit": ([P, ctypes.POINTER(_Reads), ctypes.POINTER(ctypes.c_uint64)], I),
+        "grim_serve_poll": ([P, U64, ctypes.POINTER(Result)], I),
+        "grim_serve_wait": ([P, U64, I, ctypes.POINTER(Result)], I),
+        "grim_serve_release": ([P, U64], I),
+        "grim_serve_cancel": ([P, U64], I),
+        "grim_serve_stats": ([P, ctypes.POINTER(ServeStats)], I),
+        "grim_serve_reset_stats": ([P], I),
+        "grim_serve_destroy": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -413,5 +453,80 @@ class Batcher:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+SERVE_CONTINUOUS = 0
+SERVE_PLAIN = 1
+
+
+class Server:
+    """Continuous-batching server over a resident index (grim_serve_* in grim.h)."""
+
+    def __init__(self, index: Index, policy: int = SERVE_CONTINUOUS, **cfg):
+        self.index = index  # keeps the index alive
+        c = ServeConfig()
+        c.policy = policy
+        for k, v in cfg.items():
+            if k == "allow_short_overlap":
+                c.flags = READS_ALLOW_SHORT_OVERLAP if v else 0
+            else:
+                setattr(c, k, v)
+        h = ctypes.c_void_p()
+        _check(lib().grim_serve_create(index.handle, ctypes.byref(c), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, reads: ReadSet) -> int:
+        """Queue a request (host numpy arrays; copied before returning). Returns its ticket."""
+        r = reads._struct()
+        t = ctypes.c_uint64()
+        _check(lib().grim_serve_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> Optional[dict]:
+        """None while pending, else the result dict (with its status)."""
+        out = Result()
+        rc = lib().grim_serve_poll(self._h, ticket, ctypes.byref(out))
+        if rc == GRIM_EAGAIN:
+            return None
+        if rc == GRIM_EINVAL and out.ticket == 0:
+            _check(rc)
+        return out.as_dict()
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> dict:
+        out = Result()
+        rc = lib().grim_serve_wait(self._h, ticket, timeout_ms, ctypes.byref(out))
+        if rc == GRIM_ETIMEDOUT:
+            raise GrimError(rc, lib().grim_last_error().decode(errors="replace"))
+        if rc == GRIM_EINVAL and out.ticket == 0:
+            _check(rc)
+        return out.as_dict()
+
+    def release(self, ticket: int):
+        _check(lib().grim_serve_release(self._h, ticket))
+
+    def cancel(self, ticket: int):
+        _check(lib().grim_serve_cancel(self._h, ticket))
+
+    def stats(self) -> dict:
+        out = ServeStats()
+        _check(lib().grim_serve_stats(self._h, ctypes.byref(out)))
+        return out.as_dict()
+
+    def reset_stats(self):
+        _check(lib().grim_serve_reset_stats(self._h))
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            lib().grim_serve_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
         except Exception:
             pass

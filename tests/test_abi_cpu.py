@@ -141,3 +141,44 @@ def test_batching_entry_points_reject_null_arguments():
     assert L.grim_tune(None, ctypes.byref(r), None, None, 0, None, ctypes.byref(t)) == grim.GRIM_EINVAL
     assert L.grim_index_get_config(None, 1, ctypes.byref(t)) == grim.GRIM_EINVAL
     assert L.grim_index_set_config(None, ctypes.byref(t)) == grim.GRIM_EINVAL
+
+
+def test_serving_entry_points_reject_null_arguments():
+    L = grim.lib()
+    h = ctypes.c_void_p()
+    res = grim.Result()
+    st = grim.ServeStats()
+    t = ctypes.c_uint64()
+    r = grim._Reads()
+    assert L.grim_serve_create(None, None, ctypes.byref(h)) == grim.GRIM_EINVAL
+    assert L.grim_serve_submit(None, ctypes.byref(r), ctypes.byref(t)) == grim.GRIM_EINVAL
+    assert L.grim_serve_poll(None, 1, ctypes.byref(res)) == grim.GRIM_EINVAL
+    assert L.grim_serve_wait(None, 1, 0, ctypes.byref(res)) == grim.GRIM_EINVAL
+    assert L.grim_serve_release(None, 1) == grim.GRIM_EINVAL
+    assert L.grim_serve_cancel(None, 1) == grim.GRIM_EINVAL
+    assert L.grim_serve_stats(None, ctypes.byref(st)) == grim.GRIM_EINVAL
+    assert L.grim_serve_reset_stats(None) == grim.GRIM_EINVAL
+    L.grim_serve_destroy(None)
+
+
+def test_serving_struct_layouts_match_header():
+    prog = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "grim.h"
+int main(void){
+ printf("%zu %zu %zu %zu %zu\n", sizeof(grim_serve_config), sizeof(grim_result), sizeof(grim_serve_stats_t), sizeof(grim_tune_result), sizeof(grim_batch_buffers));
+ printf("%zu %zu %zu\n", offsetof(grim_serve_config, flags), offsetof(grim_result, latency_ms), offsetof(grim_serve_stats_t, reads_per_s));
+ return 0; }
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "s.c")
+        open(c, "w").write(prog)
+        exe = os.path.join(d, "s")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        lines = subprocess.check_output([exe], text=True).split("\n")
+    assert [int(x) for x in lines[0].split()] == [ctypes.sizeof(grim.ServeConfig), ctypes.sizeof(grim.Result),
+                                                 ctypes.sizeof(grim.ServeStats), ctypes.sizeof(grim.TuneResult),
+                                                 ctypes.sizeof(grim.BatchBuffers)]
+    assert [int(x) for x in lines[1].split()] == [grim.ServeConfig.flags.offset, grim.Result.latency_ms.offset,
+                                                 grim.ServeStats.reads_per_s.offset]
