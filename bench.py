@@ -347,6 +347,8 @@ def serving(args, ref, idx, info):
                 exact[0] = False
             del m
         results[name] = {"requests": st["completed"], "failed": st["failed"], "launches": st["launches"],
+                         "shared_launches": st["shared_launches"],
+                         "max_requests_per_launch": st["max_requests_per_launch"],
                          "reads_per_s": st["reads_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
                          "max_ms": st["max_ms"], "mean_ms": st["mean_ms"],
                          "peak_device_gb": st["peak_device_bytes"] / 1e9,

@@ -309,6 +309,8 @@ typedef struct {
   uint64_t submitted, completed, failed, rejected, canceled;
   uint64_t reads_completed;
   uint64_t launches;          /* scan launches made */
+  uint64_t shared_launches;   /* launches that held reads of two or more requests */
+  uint64_t max_requests_per_launch;
   uint64_t peak_device_bytes; /* high-water mark of the arena in use */
   uint64_t arena_bytes;
   double p50_ms, p99_ms, max_ms, mean_ms; /* latency of completed requests (nearest rank) */

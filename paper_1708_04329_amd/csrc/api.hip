@@ -128,6 +128,8 @@ void free_workspace(grim_workspace& ws) {
   if (ws.status) (void)hipFree(ws.status);
   if (ws.status_host) (void)hipHostFree(ws.status_host);
   if (ws.staging) (void)hipFree(ws.staging);
+  if (ws.order) (void)hipFree(ws.order);
+  if (ws.hist) (void)hipFree(ws.hist);
   ws = grim_workspace{};
 }
 
@@ -241,6 +243,7 @@ ScanConfig scan_config_from_env(ScanConfig c) {
   if (const char* t = std::getenv("GRIM_SCAN_CHUNK")) c.reads_per_chunk = std::atoi(t);
   if (const char* t = std::getenv("GRIM_SCAN_LANE_WORDS")) c.lane_words = std::atoi(t);
   if (c.threads != 256 && c.threads != 512 && c.threads != 1024) c.threads = 1024;
+  if (const char* t = std::getenv("GRIM_SCAN_SORT")) c.sort_by_length = std::atoi(t) ? 1 : 0;
   if (c.lane_words != 4 && c.lane_words != 8) c.lane_words = 4;
   if (c.reads_per_chunk < 64) c.reads_per_chunk = 64;
   return c;
@@ -557,9 +560,17 @@ int grim_filter_scan(const grim_index* cidx, const grim_reads* rd, uint32_t* mas
   a.counts_out = counts_out;
   a.counts_bytes = counts_bytes;
   a.status = idx->ws.status;
+  const ScanConfig cfg = scan_config_from_env(idx->scan_cfg);
+  if (cfg.sort_by_length) {
+    rc = grow(&idx->ws.order, &idx->ws.order_cap, rd->n_reads);
+    if (rc) return rc;
+    if (!idx->ws.hist) GRIM_HIP_TRY(hipMalloc(&idx->ws.hist, length_order_scratch_words() * sizeof(uint32_t)));
+    GRIM_HIP_TRY(launch_length_order(v.offsets, rd->n_reads, idx->q, nullptr, idx->ws.hist, idx->ws.order, s));
+    a.read_order = idx->ws.order;
+  }
   ProfSpan ps(PROF_SCAN);
   ps.start(s);
-  GRIM_HIP_TRY(launch_scan_allbins(a, scan_config_from_env(idx->scan_cfg), s));
+  GRIM_HIP_TRY(launch_scan_allbins(a, cfg, s));
   ps.stop(s);
   rc = finish_status(idx, s);
   pt.collect();

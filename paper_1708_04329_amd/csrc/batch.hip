@@ -364,6 +364,8 @@ struct grim_batch_slot {
   uint32_t* d_mask = nullptr;
   uint32_t* d_tokens = nullptr;
   int32_t* d_thr = nullptr;
+  uint32_t* d_order = nullptr;
+  uint32_t* d_hist = nullptr;
   DynSizes* d_dyn = nullptr;
   uint32_t* d_status = nullptr;
   // the captured kernel sequence
@@ -392,7 +394,7 @@ void free_slot(grim_batch_slot& s) {
     if (p) (void)hipHostFree(p);
   for (void* p : {(void*)s.d_bases, (void*)s.d_offsets, (void*)s.d_edits, (void*)s.d_cand_off, (void*)s.d_cand_bin,
                   (void*)s.d_count, (void*)s.d_pass, (void*)s.d_mask, (void*)s.d_tokens, (void*)s.d_thr,
-                  (void*)s.d_dyn, (void*)s.d_status})
+                  (void*)s.d_order, (void*)s.d_hist, (void*)s.d_dyn, (void*)s.d_status})
     if (p) (void)hipFree(p);
   if (s.stream) (void)hipStreamDestroy(s.stream);
   s = grim_batch_slot{};
@@ -436,6 +438,8 @@ int build_slot(grim_batcher* b, grim_batch_slot& s) {
     GRIM_HIP_TRY(dev_alloc(&s.d_pass, b->max_cand));
   } else {
     GRIM_HIP_TRY(dev_alloc(&s.d_mask, b->max_reads * idx->W));
+    GRIM_HIP_TRY(dev_alloc(&s.d_order, b->max_reads));
+    GRIM_HIP_TRY(dev_alloc(&s.d_hist, length_order_scratch_words()));
   }
   std::memset(s.h_dyn, 0, sizeof(DynSizes));
 
@@ -499,7 +503,11 @@ int build_slot(grim_batcher* b, grim_batch_slot& s) {
       a.n_reads = b->max_reads;
       a.mask_out = s.d_mask;
       a.status = s.d_status;
-      e = launch_scan_allbins(a, idx->scan_cfg, s.stream);
+      if (idx->scan_cfg.sort_by_length) {
+        e = launch_length_order(s.d_offsets, b->max_reads, idx->q, s.d_dyn, s.d_hist, s.d_order, s.stream);
+        a.read_order = s.d_order;
+      }
+      if (e == hipSuccess) e = launch_scan_allbins(a, idx->scan_cfg, s.stream);
     }
   }
   hipError_t ec = hipStreamEndCapture(s.stream, &kernels);

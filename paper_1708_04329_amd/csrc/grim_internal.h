@@ -134,7 +134,14 @@ struct ScanConfig {
   int threads = 1024;         // threads per workgroup (16 waves: 4 per SIMD)
   int reads_per_chunk = 4096; // reads per workgroup
   int lane_words = 4;         // uint32 words (x32 bins) per lane: 4 or 8
+  int sort_by_length = 1;     // process reads longest first (launch_length_order)
 };
+// Sort reads 0..n-1 by their number of 32-token blocks, longest first, into
+// order[]; hist needs length_order_scratch_words() words of scratch. Kernels
+// only (graph-safe).
+uint64_t length_order_scratch_words();
+hipError_t launch_length_order(const int64_t* offsets, uint64_t n, uint32_t q, const DynSizes* dyn, uint32_t* hist,
+                               uint32_t* order, hipStream_t s);
 // Shift that turns a token code into the LDS byte offset of its tile row.
 inline uint32_t scan_token_shift(uint32_t q) {
   const int tw = tm_tile_words(q);
@@ -202,6 +209,9 @@ struct grim_workspace {
   uint32_t* status_host = nullptr; // pinned [8]
   uint8_t* staging = nullptr;      // device copies of host-resident inputs
   uint64_t staging_cap = 0;
+  uint32_t* order = nullptr;       // scan order (reads sorted by length)
+  uint64_t order_cap = 0;
+  uint32_t* hist = nullptr;        // 64 words of sort scratch
 };
 
 struct grim_index {

@@ -11,10 +11,12 @@
 //      (token list, mask row, token count, threshold);
 //   3. forms launches: the continuous policy takes up to max_batch_reads reads
 //      from all prepared requests, at most slice_reads from each, gathers
-//      their descriptors into a launch buffer and runs the all-bins scan on
-//      one of n_streams streams, so requests that arrive while others run
-//      share launches and overlap on the device; the plain policy runs each
-//      request alone, in arrival order, as one launch on one stream;
+//      their descriptors into a launch buffer, orders them by length (so a
+//      wavefront's reads have equal loop counts: reads of 100, 150 and 250 bp
+//      arrive mixed) and runs the all-bins scan on one of n_streams streams,
+//      so requests that arrive while others run share launches and overlap on
+//      the device; the plain policy runs each request alone, in arrival
+//      order, as one launch on one stream;
 //   4. completes a request when the launches holding its last reads have
 //      finished, recording its latency from submit.
 // Results stay in device memory until the client releases them. The
@@ -83,6 +85,33 @@ __global__ void k_gather_desc(SegTable t, ReadDesc* dst) {
   dst[k] = t.seg[s].src[t.seg[s].first + j];
 }
 
+// Order a launch's reads by their number of 32-token blocks, longest first,
+// so the reads sharing a wavefront have (nearly) the same loop count and the
+// long ones start first. One workgroup; counting sort over 64 buckets.
+__global__ __launch_bounds__(1024) void k_sort_desc(const ReadDesc* desc, uint32_t n, uint32_t* order) {
+  __shared__ uint32_t hist[64];
+  if (threadIdx.x < 64) hist[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
+    const uint32_t b = min((desc[k].ntok + 31) >> 5, 63u);
+    atomicAdd(&hist[63 - b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int i = 0; i < 64; ++i) {
+      const uint32_t c = hist[i];
+      hist[i] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
+    const uint32_t b = min((desc[k].ntok + 31) >> 5, 63u);
+    order[atomicAdd(&hist[63 - b], 1u)] = k;
+  }
+}
+
 enum class RState { Queued, Prepping, Active, Done, Failed, Canceled };
 
 struct Request {
@@ -109,6 +138,7 @@ struct Request {
 
 struct LaunchSlot {
   ReadDesc* desc = nullptr;
+  uint32_t* order = nullptr;  // launch position -> descriptor, sorted by length
   hipEvent_t done = nullptr;
   bool busy = false;
   uint32_t stream = 0;
@@ -147,7 +177,7 @@ struct grim_server {
   uint32_t admitted = 0;  // prepping + active
   // stats
   uint64_t n_submitted = 0, n_completed = 0, n_failed = 0, n_rejected = 0, n_canceled = 0, reads_completed = 0;
-  uint64_t launches = 0, peak_dev = 0;
+  uint64_t launches = 0, peak_dev = 0, shared_launches = 0, max_reqs_per_launch = 0;
   std::vector<double> latencies;
   bool have_first = false;
   grim::Clock::time_point t_first_submit, t_last_done;
@@ -267,8 +297,14 @@ hipError_t start_launch(grim_server* S, LaunchSlot& L, std::vector<serve::Segmen
   hipLaunchKernelGGL(k_gather_desc, dim3((total + 255) / 256), dim3(256), 0, s, t, L.desc);
   hipError_t e = hipGetLastError();
   if (e) return e;
+  const bool sorted = S->cfg.policy == GRIM_SERVE_CONTINUOUS;
+  if (sorted) {
+    hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, s, L.desc, total, L.order);
+    if ((e = hipGetLastError())) return e;
+  }
   ScanArgs a{};
   a.desc = L.desc;
+  a.read_order = sorted ? L.order : nullptr;
   a.tm = idx->tm;
   a.row_words = idx->row_words;
   a.R4 = idx->R4;
@@ -280,6 +316,8 @@ hipError_t start_launch(grim_server* S, LaunchSlot& L, std::vector<serve::Segmen
   if ((e = launch_scan_allbins(a, idx->scan_cfg, s))) return e;
   if ((e = hipEventRecord(L.done, s))) return e;
   for (auto& sg : segs) S->reqs[sg.req]->launches_in_flight++;
+  S->shared_launches += segs.size() > 1;
+  S->max_reqs_per_launch = std::max<uint64_t>(S->max_reqs_per_launch, segs.size());
   L.segs = std::move(segs);
   L.busy = true;
   S->launches++;
@@ -437,6 +475,7 @@ void release_all(grim_server* S) {
   if (S->status_pinned) (void)hipHostFree(S->status_pinned);
   for (auto& L : S->slots) {
     if (L.desc) (void)hipFree(L.desc);
+    if (L.order) (void)hipFree(L.order);
     if (L.done) (void)hipEventDestroy(L.done);
   }
   for (auto s : S->streams) (void)hipStreamDestroy(s);
@@ -503,6 +542,8 @@ extern "C" int grim_serve_create(const grim_index* idx, const grim_serve_config*
   for (auto& L : S->slots) {
     if ((e = hipMalloc(reinterpret_cast<void**>(&L.desc), desc_cap * sizeof(ReadDesc))))
       return fail(GRIM_ENOMEM, "launch descriptors", e);
+    if ((e = hipMalloc(reinterpret_cast<void**>(&L.order), desc_cap * sizeof(uint32_t))))
+      return fail(GRIM_ENOMEM, "launch order", e);
     if ((e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming))) return fail(GRIM_EDEVICE, "event", e);
   }
   grim_server* raw = S.release();
@@ -657,6 +698,8 @@ extern "C" int grim_serve_stats(grim_server* S, grim_serve_stats_t* out) {
   out->canceled = S->n_canceled;
   out->reads_completed = S->reads_completed;
   out->launches = S->launches;
+  out->shared_launches = S->shared_launches;
+  out->max_requests_per_launch = S->max_reqs_per_launch;
   out->peak_device_bytes = S->peak_dev;
   out->arena_bytes = S->cfg.arena_bytes;
   out->p50_ms = serve::nearest_rank(S->latencies, 50.0);
@@ -677,7 +720,7 @@ extern "C" int grim_serve_reset_stats(grim_server* S) {
   if (!S) return set_error(GRIM_EINVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(S->mu);
   S->n_submitted = S->n_completed = S->n_failed = S->n_rejected = S->n_canceled = S->reads_completed = 0;
-  S->launches = 0;
+  S->launches = S->shared_launches = S->max_reqs_per_launch = 0;
   S->peak_dev = S->dev_arena.used();
   S->latencies.clear();
   S->have_first = false;

@@ -102,7 +102,8 @@ class Result(ctypes.Structure):
 class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
                 ("rejected", ctypes.c_uint64), ("canceled", ctypes.c_uint64), ("reads_completed", ctypes.c_uint64),
-                ("launches", ctypes.c_uint64), ("peak_device_bytes", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("shared_launches", ctypes.c_uint64),
+                ("max_requests_per_launch", ctypes.c_uint64), ("peak_device_bytes", ctypes.c_uint64),
                 ("arena_bytes", ctypes.c_uint64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("mean_ms", ctypes.c_double), ("reads_per_s", ctypes.c_double),
                 ("queued", ctypes.c_uint32), ("admitted", ctypes.c_uint32)]

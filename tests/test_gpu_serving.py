@@ -85,12 +85,13 @@ def test_served_masks_equal_alone(world, policy):
         assert np.array_equal(got, alone(idx, sub)), (t, sub.n)
         srv.release(t)
     st = srv.stats()
-    log("policy", policy, {k: st[k] for k in ("completed", "launches", "p50_ms", "p99_ms", "peak_device_bytes")})
+    log("policy", policy, {k: st[k] for k in ("completed", "launches", "shared_launches", "max_requests_per_launch",
+                                              "p50_ms", "p99_ms", "peak_device_bytes")})
     assert st["completed"] == len(reqs) and st["failed"] == 0
     if policy == grim.SERVE_CONTINUOUS:
-        assert st["launches"] < len(reqs)       # requests shared launches
+        assert st["shared_launches"] > 0 and st["max_requests_per_launch"] > 1   # requests shared launches
     else:
-        assert st["launches"] == len(reqs)      # one launch per request
+        assert st["launches"] == len(reqs) and st["shared_launches"] == 0       # one launch per request
     srv.destroy()
 
 
