@@ -190,6 +190,8 @@ typedef struct {
   uint32_t cand_persistent;    /* candidates: 1 = fixed grid with reads handed out by an atomic
                                   counter (uneven reads in one persistent launch) */
   uint32_t cand_groups_per_cu; /* candidates, persistent: workgroups per CU in the fixed grid */
+  uint32_t cand_coop;          /* candidates, q >= 5: 1 = 4^q/512 lanes share a pair, each streaming
+                                  64 contiguous bytes of the bin vector; 0 = one lane per pair */
   uint32_t n_tried;            /* grim_tune: shapes timed */
   double best_ms;              /* grim_tune: kernel time of the chosen shape on the sample */
   double default_ms;           /* grim_tune: kernel time of the default shape on the sample */

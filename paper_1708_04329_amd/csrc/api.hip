@@ -253,6 +253,7 @@ CandConfig cand_config_from_env(CandConfig c) {
   if (const char* t = std::getenv("GRIM_CAND_WAVES")) c.waves = std::atoi(t);
   if (const char* t = std::getenv("GRIM_CAND_PERSISTENT")) c.persistent = std::atoi(t) ? 1 : 0;
   if (const char* t = std::getenv("GRIM_CAND_GROUPS_PER_CU")) c.groups_per_cu = std::atoi(t);
+  if (const char* t = std::getenv("GRIM_CAND_COOP")) c.coop = std::atoi(t) ? 1 : 0;
   if (c.waves < 0 || c.waves > 8) c.waves = 0;
   if (c.groups_per_cu < 1 || c.groups_per_cu > 64) c.groups_per_cu = 2;
   return c;

@@ -80,8 +80,8 @@ void cache_store(const std::string& key, const grim_tune_result& r) {
       if (l.rfind(key + " ", 0) != 0) lines.push_back(l);
   }
   char buf[256];
-  std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %u %.6f", key.c_str(), r.threads, r.reads_per_chunk,
-                r.lane_words, r.cand_waves, r.cand_persistent, r.cand_groups_per_cu, r.best_ms);
+  std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %u %u %.6f", key.c_str(), r.threads, r.reads_per_chunk,
+                r.lane_words, r.cand_waves, r.cand_persistent, r.cand_groups_per_cu, r.cand_coop, r.best_ms);
   lines.push_back(buf);
   std::ofstream out(path, std::ios::trunc);
   for (auto& l : lines) out << l << "\n";
@@ -97,7 +97,7 @@ bool cache_load(const std::string& key, grim_tune_result* r) {
     std::istringstream ss(l.substr(key.size() + 1));
     grim_tune_result t{};
     if (ss >> t.threads >> t.reads_per_chunk >> t.lane_words >> t.cand_waves >> t.cand_persistent >>
-        t.cand_groups_per_cu >> t.best_ms) {
+        t.cand_groups_per_cu >> t.cand_coop >> t.best_ms) {
       *r = t;
       return true;
     }
@@ -114,6 +114,7 @@ void to_result(const grim_index* idx, uint32_t mode, grim_tune_result* r) {
   r->cand_waves = (uint32_t)idx->cand_cfg.waves;
   r->cand_persistent = (uint32_t)idx->cand_cfg.persistent;
   r->cand_groups_per_cu = (uint32_t)idx->cand_cfg.groups_per_cu;
+  r->cand_coop = (uint32_t)idx->cand_cfg.coop;
 }
 
 int apply_result(grim_index* idx, const grim_tune_result* r) {
@@ -132,6 +133,8 @@ int apply_result(grim_index* idx, const grim_tune_result* r) {
     if (r->cand_persistent > 1) return set_error(GRIM_EINVAL, "cand_persistent must be 0 or 1");
     if (r->cand_groups_per_cu < 1 || r->cand_groups_per_cu > 64)
       return set_error(GRIM_EINVAL, "cand_groups_per_cu must be in [1, 64]");
+    if (r->cand_coop > 1) return set_error(GRIM_EINVAL, "cand_coop must be 0 or 1");
+    idx->cand_cfg.coop = (int)r->cand_coop;
     idx->cand_cfg.waves = (int)r->cand_waves;
     idx->cand_cfg.persistent = (int)r->cand_persistent;
     idx->cand_cfg.groups_per_cu = (int)r->cand_groups_per_cu;
@@ -258,6 +261,7 @@ extern "C" int grim_tune(grim_index* idx, const grim_reads* rd, const int64_t* c
     best.cand_waves = (uint32_t)idx->cand_cfg.waves;
     best.cand_persistent = (uint32_t)idx->cand_cfg.persistent;
     best.cand_groups_per_cu = (uint32_t)idx->cand_cfg.groups_per_cu;
+    best.cand_coop = (uint32_t)idx->cand_cfg.coop;
   } else {
     DevBuf<uint16_t> cnt;
     DevBuf<uint8_t> pas;
@@ -283,25 +287,29 @@ extern "C" int grim_tune(grim_index* idx, const grim_reads* rd, const int64_t* c
     a.status = idx->ws.status;
     a.work = idx->ws.status + 4;
     const int waves[] = {1, 2, 4, 8};
-    for (int nw : waves)
-      for (int pers = 0; pers <= 1; ++pers)
-        for (int gpc : {2, 4, 8, 16}) {
-          if (!pers && gpc != 2) continue;
-          CandConfig c;
-          c.waves = nw;
-          c.persistent = pers;
-          c.groups_per_cu = gpc;
-          const double ms = time_it([&] { return launch_scan_candidates(a, c, s); });
-          if (ms < 0) continue;
-          ++tried;
-          if (nw == 8 && !pers) default_ms = ms;
-          if (ms < best.best_ms) {
-            best.best_ms = ms;
-            best.cand_waves = (uint32_t)nw;
-            best.cand_persistent = (uint32_t)pers;
-            best.cand_groups_per_cu = (uint32_t)gpc;
+    const CandConfig dflt;
+    for (int coop = 0; coop <= (idx->vec_words >= 32 ? 1 : 0); ++coop)
+      for (int nw : waves)
+        for (int pers = 0; pers <= 1; ++pers)
+          for (int gpc : {2, 4, 8, 16}) {
+            if (!pers && gpc != 2) continue;
+            CandConfig c;
+            c.waves = nw;
+            c.persistent = pers;
+            c.groups_per_cu = gpc;
+            c.coop = coop;
+            const double ms = time_it([&] { return launch_scan_candidates(a, c, s); });
+            if (ms < 0) continue;
+            ++tried;
+            if (coop == (idx->vec_words >= 32 ? dflt.coop : 0) && nw == 4 && !pers) default_ms = ms;
+            if (ms < best.best_ms) {
+              best.best_ms = ms;
+              best.cand_waves = (uint32_t)nw;
+              best.cand_persistent = (uint32_t)pers;
+              best.cand_groups_per_cu = (uint32_t)gpc;
+              best.cand_coop = (uint32_t)coop;
+            }
           }
-        }
     best.threads = (uint32_t)idx->scan_cfg.threads;
     best.reads_per_chunk = (uint32_t)idx->scan_cfg.reads_per_chunk;
     best.lane_words = (uint32_t)idx->scan_cfg.lane_words;

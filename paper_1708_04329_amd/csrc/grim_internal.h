@@ -172,6 +172,7 @@ struct CandConfig {
   int waves = 0;         // wavefronts per workgroup (0: by vector size)
   int persistent = 0;    // 1: fixed grid, reads handed out by an atomic counter
   int groups_per_cu = 2; // persistent grid size = 256 CUs x groups_per_cu
+  int coop = 1;          // 1: VW/16 lanes per pair (q >= 5), 0: one lane per pair
 };
 hipError_t launch_scan_candidates(const CandArgs& a, const CandConfig& cfg, hipStream_t s);
 // Zero `n` uint32 words with a kernel (graph-safe, unlike a memset node).

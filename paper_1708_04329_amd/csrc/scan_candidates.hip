@@ -12,6 +12,13 @@
 // wave-uniform address, i.e. a broadcast), counting with v_bcnt. The gather
 // of one bin vector per pair is the compulsory traffic of this mode.
 //
+// Two lane layouts: one lane per pair (the lane streams the whole vector), or
+// a group of G = VW/16 lanes per pair, each lane streaming 64 contiguous bytes
+// of the vector (so one wavefront load touches 64/G vectors instead of 64
+// scattered ones) with its slice of the planes kept in registers for all of
+// the read's pairs, and the partial counts summed across the group with
+// xor-shuffles.
+//
 // Two launch shapes: one wavefront per read (the hardware dispatcher
 // balances), or a persistent grid whose wavefronts take the next read from an
 // atomic counter until none are left (reads of uneven length and candidate
@@ -30,20 +37,23 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Steps 1-3 for read r: histogram of its tokens and the K multiplicity planes
+// in this wavefront's LDS. Returns K, or -1 when the read has no candidates.
 template <int VW>
-__device__ __forceinline__ void cand_read(const CandArgs& a, uint64_t r, uint64_t n_cand, uint32_t* hist,
-                                          uint32_t* planes, uint32_t lane) {
+__device__ __forceinline__ int build_planes(const CandArgs& a, uint64_t r, uint64_t n_cand, uint32_t* hist,
+                                            uint32_t* planes, uint32_t lane, int64_t* pc0, int64_t* pc1) {
   constexpr uint32_t kHistWords = VW * 16;  // R4 / 2 packed uint16 counters (R4 = 32*VW)
   const int64_t c0 = a.cand_off[r], c1 = a.cand_off[r + 1];
   if (c0 < 0 || c1 < c0 || (uint64_t)c1 > n_cand) {
     if (lane == 0) atomicOr(a.status, ST_BAD_CAND_OFF);
-    return;
+    return -1;
   }
-  if (c0 == c1) return;
+  if (c0 == c1) return -1;
+  *pc0 = c0;
+  *pc1 = c1;
   const int64_t o0 = a.offsets[r], o1 = a.offsets[r + 1];
   const uint32_t ntok = (uint32_t)(o1 - o0 - a.q + 1);
   const uint32_t* tok = a.tokens + token_base(o0, r);
-  const int32_t T = a.thr[r];
   const uint32_t R4 = a.R4;
 
   // 1. token histogram (uint16 counters packed in pairs)
@@ -78,6 +88,17 @@ __device__ __forceinline__ void cand_read(const CandArgs& a, uint64_t r, uint64_
     }
   }
   wave_sync();
+  return (int)K;
+}
+
+template <int VW>
+__device__ __forceinline__ void cand_read(const CandArgs& a, uint64_t r, uint64_t n_cand, uint32_t* hist,
+                                          uint32_t* planes, uint32_t lane) {
+  int64_t c0 = 0, c1 = 0;
+  const int Ki = build_planes<VW>(a, r, n_cand, hist, planes, lane, &c0, &c1);
+  if (Ki < 0) return;
+  const uint32_t K = (uint32_t)Ki;
+  const int32_t T = a.thr[r];
   // 4. one candidate per lane
   for (int64_t cb = c0; cb < c1; cb += 64) {
     const int64_t c = cb + lane;
@@ -126,7 +147,80 @@ __device__ __forceinline__ void cand_read(const CandArgs& a, uint64_t r, uint64_
   wave_sync();
 }
 
-template <int VW, int NW, bool PERSISTENT>
+// Cooperative layout: G = VW / 16 lanes per pair, lane j streams words
+// [16j, 16j + 16) of the bin's vector and keeps the same words of the first
+// four planes in registers for all of the read's pairs.
+template <int VW>
+__device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, uint64_t n_cand, uint32_t* hist,
+                                               uint32_t* planes, uint32_t lane) {
+  constexpr int G = VW / 16;
+  constexpr int PPW = 64 / G;  // pairs per wavefront pass
+  int64_t c0 = 0, c1 = 0;
+  const int Ki = build_planes<VW>(a, r, n_cand, hist, planes, lane, &c0, &c1);
+  if (Ki < 0) return;
+  const uint32_t K = (uint32_t)Ki;
+  const int32_t T = a.thr[r];
+  const uint32_t j = lane % G, g = lane / G;
+  uint32_t pl[4][16];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if ((uint32_t)k < K) {
+#pragma unroll
+      for (int w4 = 0; w4 < 4; ++w4) {
+        const uint4 p = reinterpret_cast<const uint4*>(planes + k * VW + 16 * j)[w4];
+        pl[k][4 * w4 + 0] = p.x; pl[k][4 * w4 + 1] = p.y; pl[k][4 * w4 + 2] = p.z; pl[k][4 * w4 + 3] = p.w;
+      }
+    } else {
+#pragma unroll
+      for (int w = 0; w < 16; ++w) pl[k][w] = 0;
+    }
+  }
+  for (int64_t cb = c0; cb < c1; cb += PPW) {
+    const int64_t c = cb + g;
+    const bool active = c < c1;
+    uint32_t part = 0;
+    bool bad = false;
+    if (active) {
+      const int32_t x = a.cand_bin[c];
+      if (x < 0 || (uint64_t)x >= a.nb) {
+        bad = true;
+      } else {
+        const uint4* v4 = reinterpret_cast<const uint4*>(a.bm + (uint64_t)x * VW + 16 * j);
+        uint32_t v[16];
+#pragma unroll
+        for (int w4 = 0; w4 < 4; ++w4) {
+          const uint4 t = v4[w4];
+          v[4 * w4 + 0] = t.x; v[4 * w4 + 1] = t.y; v[4 * w4 + 2] = t.z; v[4 * w4 + 3] = t.w;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if ((uint32_t)k < K) {  // wave-uniform
+            uint32_t acc = 0;
+#pragma unroll
+            for (int w = 0; w < 16; ++w) acc += __popc(v[w] & pl[k][w]);
+            part += acc << k;
+          }
+        }
+        for (uint32_t k = 4; k < K; ++k) {  // rare: a token repeated 16 times or more
+          uint32_t acc = 0;
+          for (int w = 0; w < 16; ++w) acc += __popc(v[w] & planes[k * VW + 16 * j + w]);
+          part += acc << k;
+        }
+      }
+    }
+    // sum the group's partial counts (groups are aligned runs of G lanes)
+#pragma unroll
+    for (int off = G / 2; off >= 1; off >>= 1) part += (uint32_t)__shfl_xor((int)part, off);
+    if (bad && j == 0) atomicOr(a.status, ST_BAD_BIN);
+    if (active && j == 0) {
+      if (a.count_out) a.count_out[c] = (uint16_t)part;
+      if (a.pass_out) a.pass_out[c] = (int32_t)part >= T ? 1 : 0;
+    }
+  }
+  wave_sync();
+}
+
+template <int VW, int NW, bool PERSISTENT, bool COOP>
 __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
   constexpr uint32_t kHistWords = VW * 16;
   constexpr uint32_t kPerWave = kHistWords + kMaxPlanes * VW;
@@ -137,9 +231,13 @@ __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
   const uint64_t n_reads = a.dyn ? min(a.dyn->n_reads, a.n_reads) : a.n_reads;
   const uint64_t n_cand = a.dyn ? min(a.dyn->n_cand, a.n_cand) : a.n_cand;
   if (a.status[0] & ~(uint32_t)(ST_BAD_BIN | ST_BAD_CAND_OFF)) return;  // rejected reads
+  auto one = [&](uint64_t r) {
+    if constexpr (COOP) cand_read_coop<VW>(a, r, n_cand, hist, planes, lane);
+    else cand_read<VW>(a, r, n_cand, hist, planes, lane);
+  };
   if constexpr (!PERSISTENT) {
     const uint64_t r = (uint64_t)blockIdx.x * NW + wave;
-    if (r < n_reads) cand_read<VW>(a, r, n_cand, hist, planes, lane);
+    if (r < n_reads) one(r);
   } else {
     // every wavefront leaves once the counter has passed n_reads
     while (true) {
@@ -147,25 +245,33 @@ __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
       if (lane == 0) r = atomicAdd(a.work, 1u);
       r = __shfl(r, 0);
       if ((uint64_t)r >= n_reads) break;
-      cand_read<VW>(a, r, n_cand, hist, planes, lane);
+      one(r);
     }
   }
 }
 
-template <int VW, int NW>
-hipError_t launch_nw(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
+template <int VW, int NW, bool COOP>
+hipError_t launch_nw_layout(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
   if (cfg.persistent) {
     if (!a.work) return hipErrorInvalidValue;
     const uint64_t blocks = 256ull * (uint64_t)max(1, cfg.groups_per_cu);
     hipError_t e = launch_zero_words(a.work, 1, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_scan_cand<VW, NW, true>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, a);
+    hipLaunchKernelGGL((k_scan_cand<VW, NW, true, COOP>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, a);
   } else {
     const uint64_t blocks = (a.n_reads + NW - 1) / NW;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_scan_cand<VW, NW, false>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, a);
+    hipLaunchKernelGGL((k_scan_cand<VW, NW, false, COOP>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, a);
   }
   return hipGetLastError();
+}
+
+template <int VW, int NW>
+hipError_t launch_nw(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
+  if constexpr (VW >= 32) {
+    if (cfg.coop) return launch_nw_layout<VW, NW, true>(a, cfg, s);
+  }
+  return launch_nw_layout<VW, NW, false>(a, cfg, s);
 }
 
 // LDS per wavefront: (16 + kMaxPlanes) * VW words; the wave count per group

@@ -69,7 +69,8 @@ class _Reads(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_uint32), ("threads", ctypes.c_uint32), ("reads_per_chunk", ctypes.c_uint32),
                 ("lane_words", ctypes.c_uint32), ("cand_waves", ctypes.c_uint32), ("cand_persistent", ctypes.c_uint32),
-                ("cand_groups_per_cu", ctypes.c_uint32), ("n_tried", ctypes.c_uint32), ("best_ms", ctypes.c_double),
+                ("cand_groups_per_cu", ctypes.c_uint32), ("cand_coop", ctypes.c_uint32),
+                ("n_tried", ctypes.c_uint32), ("best_ms", ctypes.c_double),
                 ("default_ms", ctypes.c_double)]
 
     def as_dict(self):

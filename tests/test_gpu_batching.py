@@ -59,12 +59,14 @@ def test_candidate_launch_shapes_agree(oracle, uneven):
     ep = rd.err_pm.astype(np.uint16)
     want = oracle.scan_candidates(oracle.bits(ref, w.bin_size, w.overlap, w.q), w.q, rd.bases, rd.offsets, co, cb,
                                   err_pm_per_read=ep)
-    for waves in (1, 2, 4):
-        for pers, gpc in ((0, 2), (1, 1), (1, 4), (1, 16)):
-            grim.grim_index_set_config(idx, {"mode": grim.MODE_CANDIDATES, "cand_waves": waves,
-                                             "cand_persistent": pers, "cand_groups_per_cu": gpc})
-            got = run_cand(idx, rd, co, cb, ep)
-            assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), (waves, pers, gpc)
+    for coop in (0, 1):
+        for waves in (1, 2, 4):
+            for pers, gpc in ((0, 2), (1, 1), (1, 4), (1, 16)):
+                grim.grim_index_set_config(idx, {"mode": grim.MODE_CANDIDATES, "cand_waves": waves,
+                                                 "cand_persistent": pers, "cand_groups_per_cu": gpc,
+                                                 "cand_coop": coop})
+                got = run_cand(idx, rd, co, cb, ep)
+                assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), (coop, waves, pers, gpc)
 
 
 def test_tune_candidates(oracle, uneven, tmp_path, monkeypatch):
@@ -147,7 +149,7 @@ def test_batcher_candidates_every_replay_matches_eager(uneven):
     w, ref, rd, co, cb, idx = uneven
     ep = rd.err_pm.astype(np.uint16)
     grim.grim_index_set_config(idx, {"mode": grim.MODE_CANDIDATES, "cand_waves": 4, "cand_persistent": 1,
-                                     "cand_groups_per_cu": 4})
+                                     "cand_groups_per_cu": 4, "cand_coop": 1})
     b = grim.Batcher(idx, grim.MODE_CANDIDATES, max_reads=2000, max_bases=2000 * 250, max_cand=2000 * 1024,
                      edits_kind=grim.BATCH_EDITS_ERR)
     rng = random.Random(3)

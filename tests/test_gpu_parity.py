@@ -195,9 +195,11 @@ def test_threshold_not_positive_passes_all_bins(oracle):
 # candidate mode
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("coop", [0, 1])
 @pytest.mark.parametrize("q", [2, 3, 4, 5, 6, 7])
-def test_candidates_match_oracle_random(oracle, q):
+def test_candidates_match_oracle_random(oracle, q, coop, monkeypatch):
     import torch
+    monkeypatch.setenv("GRIM_CAND_COOP", str(coop))
     rng = random.Random(500 + q)
     B = 61
     G = 150000 if q <= 6 else 40000
