@@ -39,8 +39,9 @@ int status_to_error(uint32_t st);
 
 // Token storage: uint32 per token. Read r's tokens start at
 // token_base(offsets[r], r) (a multiple of 32 tokens) and are padded with the
-// code R4 = 4^q up to a multiple of 32. Each entry holds code << tok_shift: the
-// all-bins scan stores the LDS byte offset of the token's row (shift =
+// code R4 = 4^q up to the next multiple of 32 above the token count (so at
+// least one padding token follows the last real one). Each entry holds
+// code << tok_shift: the all-bins scan stores the LDS byte offset of the token's row (shift =
 // log2(tile words * 4)), candidate checks store the plain code (shift 0).
 // The regions of consecutive reads never overlap, and the buffer needs
 // token_capacity(n_bases, n_reads) entries.

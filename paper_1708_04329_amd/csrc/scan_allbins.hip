@@ -22,6 +22,13 @@
 // row, so a row address costs one add per token. Workgroup ids are remapped
 // so the 32 CUs of one XCD work on the tiles of the same read chunk, whose
 // tokens then stay in that XCD's L2.
+//
+// Full 32-token blocks go through the Harley-Seal tree; the remainder of a
+// read is folded exactly as power-of-two parts, so no padding token costs
+// work unless another read of the wavefront needs that part. Counters have
+// 8 planes (counts up to 255); a wavefront holding a longer read switches to
+// 16 planes and covers its words in 2-word passes, which keeps that path
+// within the registers of the common one.
 
 #include "grim_internal.h"
 
@@ -77,60 +84,86 @@ struct Counters {
   uint32_t p[5 + NHI][LW];
 };
 
-// Fold 32 tokens (tk[i] = LDS byte offset of token i's row) into the counters.
-template <int LW, int NHI>
-__device__ __forceinline__ void fold32(Counters<LW, NHI>& c, const char* lds_lane, const uint32_t (&tk)[32]) {
-  auto row = [&](int i) -> Words<LW> {
-    return lds_row<LW>(reinterpret_cast<const uint32_t*>(lds_lane + tk[i]));
-  };
-  uint32_t s16a[LW], s16b[LW];
+// Carry-save tree over N = 2^k tokens (tk[i] = LDS byte offset of token i's
+// row): the tokens' rows are folded into planes 0..k-1 and the carry of
+// weight N is returned in out[]. tree<32> is Harley-Seal over a 32-token block:
+// 31 full adders per word.
+template <int N, int LW, int NHI>
+__device__ __forceinline__ void tree(Counters<LW, NHI>& c, const char* lds_lane, const uint32_t* tk,
+                                     uint32_t (&out)[LW]) {
+  if constexpr (N == 2) {
+    const Words<LW> x0 = lds_row<LW>(reinterpret_cast<const uint32_t*>(lds_lane + tk[0]));
+    const Words<LW> x1 = lds_row<LW>(reinterpret_cast<const uint32_t*>(lds_lane + tk[1]));
 #pragma unroll
-  for (int h16 = 0; h16 < 2; ++h16) {
-    uint32_t e8a[LW], e8b[LW];
+    for (int j = 0; j < LW; ++j) CSA(out[j], c.p[0][j], c.p[0][j], x0.w[j], x1.w[j]);
+  } else {
+    constexpr int L = (N == 4) ? 1 : (N == 8) ? 2 : (N == 16) ? 3 : 4;  // level of the two halves' carries
+    uint32_t a[LW], b[LW];
+    tree<N / 2, LW, NHI>(c, lds_lane, tk, a);
+    tree<N / 2, LW, NHI>(c, lds_lane, tk + N / 2, b);
 #pragma unroll
-    for (int h8 = 0; h8 < 2; ++h8) {
-      uint32_t f4a[LW], f4b[LW];
-#pragma unroll
-      for (int h4 = 0; h4 < 2; ++h4) {
-        const int i0 = h16 * 16 + h8 * 8 + h4 * 4;
-        const Words<LW> x0 = row(i0), x1 = row(i0 + 1), x2 = row(i0 + 2), x3 = row(i0 + 3);
-        uint32_t t2a[LW], t2b[LW];
-#pragma unroll
-        for (int j = 0; j < LW; ++j) {
-          CSA(t2a[j], c.p[0][j], c.p[0][j], x0.w[j], x1.w[j]);
-          CSA(t2b[j], c.p[0][j], c.p[0][j], x2.w[j], x3.w[j]);
-          if (h4 == 0) CSA(f4a[j], c.p[1][j], c.p[1][j], t2a[j], t2b[j]);
-          else CSA(f4b[j], c.p[1][j], c.p[1][j], t2a[j], t2b[j]);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < LW; ++j) {
-        if (h8 == 0) CSA(e8a[j], c.p[2][j], c.p[2][j], f4a[j], f4b[j]);
-        else CSA(e8b[j], c.p[2][j], c.p[2][j], f4a[j], f4b[j]);
-      }
-      // keep the scheduler from hoisting the next 8 tokens' LDS loads above
-      // this point: with 8 words per lane, 32 tokens of loads in flight would
-      // not fit the register file
-      if constexpr (LW >= 8) __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int j = 0; j < LW; ++j) {
-      if (h16 == 0) CSA(s16a[j], c.p[3][j], c.p[3][j], e8a[j], e8b[j]);
-      else CSA(s16b[j], c.p[3][j], c.p[3][j], e8a[j], e8b[j]);
-    }
+    for (int j = 0; j < LW; ++j) CSA(out[j], c.p[L][j], c.p[L][j], a[j], b[j]);
+    // keep the scheduler from hoisting later LDS loads above this point: with
+    // 8 words per lane, 32 tokens of loads in flight would not fit the VGPRs
+    if constexpr (LW >= 8 && N == 8) __builtin_amdgcn_sched_barrier(0);
   }
+}
+
+// Add a carry of weight 2^L (one bit per bin) to the counters: half adders up
+// through planes L..4, then the binary planes of weight 32 and up.
+template <int L, int LW, int NHI>
+__device__ __forceinline__ void add_carry(Counters<LW, NHI>& c, const uint32_t (&carry_in)[LW]) {
 #pragma unroll
   for (int j = 0; j < LW; ++j) {
-    uint32_t carry;
-    CSA(carry, c.p[4][j], c.p[4][j], s16a[j], s16b[j]);
-    // ripple the multiple of 32 into the high planes
+    uint32_t carry = carry_in[j];
 #pragma unroll
-    for (int k = 0; k < NHI; ++k) {
-      const uint32_t h = c.p[5 + k][j];
-      c.p[5 + k][j] = h ^ carry;
-      if (k + 1 < NHI) carry = h & carry;
+    for (int k = L; k < 5 + NHI; ++k) {
+      const uint32_t h = c.p[k][j];
+      c.p[k][j] = h ^ carry;
+      if (k + 1 < 5 + NHI) carry = h & carry;
     }
   }
+}
+
+// Fold 32 tokens into the counters.
+template <int LW, int NHI>
+__device__ __forceinline__ void fold32(Counters<LW, NHI>& c, const char* lds_lane, const uint32_t (&tk)[32]) {
+  uint32_t carry[LW];
+  tree<32, LW, NHI>(c, lds_lane, tk, carry);
+  add_carry<5, LW, NHI>(c, carry);
+}
+
+// Load N = 2^k token offsets from global memory at `src` (16-byte aligned
+// for N >= 4); lanes that are not active take the all-zero row.
+template <int N>
+__device__ __forceinline__ void load_part(uint32_t (&tk)[N], const uint32_t* src, bool active, uint32_t zero_off) {
+  if constexpr (N >= 4) {
+#pragma unroll
+    for (int i = 0; i < N / 4; ++i) {
+      uint4 v = make_uint4(zero_off, zero_off, zero_off, zero_off);
+      if (active) v = reinterpret_cast<const uint4*>(src)[i];
+      tk[4 * i + 0] = v.x; tk[4 * i + 1] = v.y; tk[4 * i + 2] = v.z; tk[4 * i + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) tk[i] = active ? src[i] : zero_off;
+  }
+}
+
+// Fold N = 2^k tokens into the counters: a tree into planes 0..k-1 whose
+// carry of weight N enters at plane k.
+template <int N, int LW, int NHI>
+__device__ __forceinline__ void fold_part(Counters<LW, NHI>& c, const char* lds_lane, const uint32_t (&tk)[N]) {
+  constexpr int L = (N == 1) ? 0 : (N == 2) ? 1 : (N == 4) ? 2 : (N == 8) ? 3 : 4;
+  uint32_t carry[LW];
+  if constexpr (N == 1) {
+    const Words<LW> x = lds_row<LW>(reinterpret_cast<const uint32_t*>(lds_lane + tk[0]));
+#pragma unroll
+    for (int j = 0; j < LW; ++j) carry[j] = x.w[j];
+  } else {
+    tree<N, LW, NHI>(c, lds_lane, tk, carry);
+  }
+  add_carry<L, LW, NHI>(c, carry);
 }
 
 // Threshold test on 32 bit-sliced counters of NP planes: bit b of the result
@@ -149,16 +182,17 @@ __device__ __forceinline__ uint32_t ge_threshold(const uint32_t (&pl)[NP], const
 template <int LW, int NHI>
 __device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lane, bool active,
                                           const uint32_t* tok, uint32_t* out_row, uint64_t rid, uint32_t ntok,
-                                          int32_t T, uint64_t gw0) {
+                                          int32_t T, uint64_t gw0, uint32_t zero_off) {
   constexpr int NP = 5 + NHI;
   Counters<LW, NHI> c;
 #pragma unroll
   for (int k = 0; k < NP; ++k)
 #pragma unroll
     for (int j = 0; j < LW; ++j) c.p[k][j] = 0;
-  const uint32_t nblk = active ? (ntok + 31) >> 5 : 0;
+  // full 32-token blocks
+  const uint32_t nfull = active ? ntok >> 5 : 0;
   const uint4* tk4 = reinterpret_cast<const uint4*>(tok);
-  for (uint32_t b = 0; b < nblk; ++b) {
+  for (uint32_t b = 0; b < nfull; ++b) {
     uint32_t tk[32];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -167,6 +201,28 @@ __device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lan
     }
     fold32<LW, NHI>(c, lds_lane, tk);
   }
+  // The last partial block, folded exactly as 16/8/4/2/1-token parts: part
+  // 2^k is folded when any lane's remainder has bit k, so the parts cover
+  // every lane's remainder, and a lane reads zero-row padding past its own
+  // (every token list ends with at least one padding token and is padded to
+  // a multiple of 32). The parts' token loads are all issued before the
+  // first fold so that their latencies overlap.
+  const uint32_t rem = active ? (ntok & 31u) : 0u;
+  const uint32_t* tail = active ? tok + (uint64_t)nfull * 32 : nullptr;
+  const bool h16 = __any(rem & 16u), h8 = __any(rem & 8u), h4 = __any(rem & 4u), h2 = __any(rem & 2u),
+             h1 = __any(rem & 1u);
+  const uint32_t p8 = h16 ? 16 : 0, p4 = p8 + (h8 ? 8 : 0), p2 = p4 + (h4 ? 4 : 0), p1 = p2 + (h2 ? 2 : 0);
+  uint32_t t16[16], t8[8], t4[4], t2[2], t1[1];
+  if (h16) load_part<16>(t16, tail, active, zero_off);
+  if (h8) load_part<8>(t8, tail + p8, active, zero_off);
+  if (h4) load_part<4>(t4, tail + p4, active, zero_off);
+  if (h2) load_part<2>(t2, tail + p2, active, zero_off);
+  if (h1) load_part<1>(t1, tail + p1, active, zero_off);
+  if (h16) fold_part<16, LW, NHI>(c, lds_lane, t16);
+  if (h8) fold_part<8, LW, NHI>(c, lds_lane, t8);
+  if (h4) fold_part<4, LW, NHI>(c, lds_lane, t4);
+  if (h2) fold_part<2, LW, NHI>(c, lds_lane, t2);
+  if (h1) fold_part<1, LW, NHI>(c, lds_lane, t1);
   if (!active) return;
   // K = 2^NP - T as NP all-ones/all-zeros masks, shared by the lane's words
   const uint32_t allpass = T <= 0 ? 0xFFFFFFFFu : 0u;
@@ -241,6 +297,7 @@ __global__ __launch_bounds__(NT) void k_scan_allbins(ScanArgs a) {
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const uint32_t g = lane / G, s = lane % G;
   const char* lds_lane = reinterpret_cast<const char*>(lds) + s * LW * 4;
+  const uint32_t zero_off = R4 * TW * 4;  // byte offset of the all-zero row
   const uint64_t gw0 = (uint64_t)tile * TW + (uint64_t)s * LW;
   const uint64_t r_begin = (uint64_t)rchunk * a.reads_per_chunk;
   uint64_t r_end = r_begin + a.reads_per_chunk;
@@ -270,8 +327,16 @@ __global__ __launch_bounds__(NT) void k_scan_allbins(ScanArgs a) {
         T = a.thr[rid];
       }
     }
-    if (__any(ntok > 255)) scan_read<LW, 11>(a, lds_lane, active, tok, out_row, rid, ntok, T, gw0);
-    else scan_read<LW, 3>(a, lds_lane, active, tok, out_row, rid, ntok, T, gw0);
+    if (__any(ntok > 255)) {
+      // 16 counter planes: two (or one) words per pass keeps the registers
+      // of this rare path within the budget of the common one
+      constexpr int LWW = LW >= 2 ? 2 : 1;
+#pragma unroll
+      for (int h = 0; h < LW / LWW; ++h)
+        scan_read<LWW, 11>(a, lds_lane + h * LWW * 4, active, tok, out_row, rid, ntok, T, gw0 + h * LWW, zero_off);
+    } else {
+      scan_read<LW, 3>(a, lds_lane, active, tok, out_row, rid, ntok, T, gw0, zero_off);
+    }
   }
 }
 

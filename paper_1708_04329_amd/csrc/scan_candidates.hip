@@ -37,11 +37,27 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Sum of x over aligned groups of G lanes (G a power of two up to 32), left
+// in every lane of the group. Within 16-lane rows the steps are DPP moves
+// (swap neighbours, swap pairs, mirror the 8-lane halves, mirror the row);
+// each step's partial sums are equal across the lanes they came from, so a
+// mirror brings in the other half's sum.
+template <int G>
+__device__ __forceinline__ uint32_t group_sum(uint32_t x) {
+  if constexpr (G >= 2) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  if constexpr (G >= 4) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+  if constexpr (G >= 8) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  if constexpr (G >= 16) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false); // row_mirror
+  if constexpr (G >= 32) x += (uint32_t)__shfl_xor((int)x, 16);
+  return x;
+}
+
 // Steps 1-3 for read r: histogram of its tokens and the K multiplicity planes
 // in this wavefront's LDS. Returns K, or -1 when the read has no candidates.
 template <int VW>
 __device__ __forceinline__ int build_planes(const CandArgs& a, uint64_t r, uint64_t n_cand, uint32_t* hist,
                                             uint32_t* planes, uint32_t lane, int64_t* pc0, int64_t* pc1) {
+  static_assert(VW <= 512, "token histogram of 4^q counters");
   constexpr uint32_t kHistWords = VW * 16;  // R4 / 2 packed uint16 counters (R4 = 32*VW)
   const int64_t c0 = a.cand_off[r], c1 = a.cand_off[r + 1];
   if (c0 < 0 || c1 < c0 || (uint64_t)c1 > n_cand) {
@@ -72,17 +88,30 @@ __device__ __forceinline__ int build_planes(const CandArgs& a, uint64_t r, uint6
   }
   for (int off = 32; off >= 1; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
   const uint32_t K = mx ? 32u - __clz(mx) : 0u;
-  // 3. planes: bit b of plane j word w = bit j of the count of token 32*w + b
-  for (uint32_t w = lane; w < VW; w += 64) {
-    uint32_t m2[16];  // counts of tokens 32w .. 32w+31, two per word
+  // 3. planes: bit b of plane j word w = bit j of the count of token 32*w + b.
+  // The planes overwrite the histogram (same LDS), so every lane first takes
+  // its words' counts into registers.
+  constexpr int kWL = VW >= 64 ? VW / 64 : 1;  // words of the vector per lane
+  uint32_t m2[kWL][16];                        // counts of tokens 32w .. 32w+31, two per word
 #pragma unroll
-    for (int i = 0; i < 16; ++i) m2[i] = hist[w * 16 + i];
+  for (int i = 0; i < kWL; ++i) {
+    const uint32_t w = lane + 64u * i;
+    if (w < VW) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) m2[i][k] = hist[w * 16 + k];
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < kWL; ++i) {
+    const uint32_t w = lane + 64u * i;
+    if (w >= VW) continue;
     for (uint32_t j = 0; j < K; ++j) {
       uint32_t pw = 0;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        pw |= ((m2[i] >> j) & 1u) << (2 * i);
-        pw |= ((m2[i] >> (16 + j)) & 1u) << (2 * i + 1);
+      for (int k = 0; k < 16; ++k) {
+        pw |= ((m2[i][k] >> j) & 1u) << (2 * k);
+        pw |= ((m2[i][k] >> (16 + j)) & 1u) << (2 * k + 1);
       }
       planes[j * VW + w] = pw;
     }
@@ -175,46 +204,56 @@ __device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, ui
       for (int w = 0; w < 16; ++w) pl[k][w] = 0;
     }
   }
-  for (int64_t cb = c0; cb < c1; cb += PPW) {
-    const int64_t c = cb + g;
-    const bool active = c < c1;
-    uint32_t part = 0;
-    bool bad = false;
-    if (active) {
-      const int32_t x = a.cand_bin[c];
-      if (x < 0 || (uint64_t)x >= a.nb) {
-        bad = true;
-      } else {
-        const uint4* v4 = reinterpret_cast<const uint4*>(a.bm + (uint64_t)x * VW + 16 * j);
-        uint32_t v[16];
+  // U pair-passes per iteration: their bin ids, then their vectors, are
+  // loaded together so that U gathers per lane are in flight at once
+  constexpr int U = 2;
+  for (int64_t cb = c0; cb < c1; cb += (int64_t)U * PPW) {
+    int64_t c[U];
+    int32_t x[U];
+    bool ok[U];
 #pragma unroll
-        for (int w4 = 0; w4 < 4; ++w4) {
-          const uint4 t = v4[w4];
-          v[4 * w4 + 0] = t.x; v[4 * w4 + 1] = t.y; v[4 * w4 + 2] = t.z; v[4 * w4 + 3] = t.w;
-        }
+    for (int u = 0; u < U; ++u) {
+      c[u] = cb + u * PPW + g;
+      x[u] = c[u] < c1 ? a.cand_bin[c[u]] : 0;
+    }
+    uint32_t v[U][16];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if ((uint32_t)k < K) {  // wave-uniform
-            uint32_t acc = 0;
+    for (int u = 0; u < U; ++u) {
+      ok[u] = c[u] < c1 && x[u] >= 0 && (uint64_t)x[u] < a.nb;
+      const uint4* v4 = reinterpret_cast<const uint4*>(a.bm + (uint64_t)(ok[u] ? x[u] : 0) * VW + 16 * j);
 #pragma unroll
-            for (int w = 0; w < 16; ++w) acc += __popc(v[w] & pl[k][w]);
-            part += acc << k;
-          }
-        }
-        for (uint32_t k = 4; k < K; ++k) {  // rare: a token repeated 16 times or more
+      for (int w4 = 0; w4 < 4; ++w4) {
+        uint4 t = make_uint4(0, 0, 0, 0);
+        if (ok[u]) t = v4[w4];
+        v[u][4 * w4 + 0] = t.x; v[u][4 * w4 + 1] = t.y; v[u][4 * w4 + 2] = t.z; v[u][4 * w4 + 3] = t.w;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t part = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if ((uint32_t)k < K) {  // wave-uniform
           uint32_t acc = 0;
-          for (int w = 0; w < 16; ++w) acc += __popc(v[w] & planes[k * VW + 16 * j + w]);
+#pragma unroll
+          for (int w = 0; w < 16; ++w) acc += __popc(v[u][w] & pl[k][w]);
           part += acc << k;
         }
       }
-    }
-    // sum the group's partial counts (groups are aligned runs of G lanes)
-#pragma unroll
-    for (int off = G / 2; off >= 1; off >>= 1) part += (uint32_t)__shfl_xor((int)part, off);
-    if (bad && j == 0) atomicOr(a.status, ST_BAD_BIN);
-    if (active && j == 0) {
-      if (a.count_out) a.count_out[c] = (uint16_t)part;
-      if (a.pass_out) a.pass_out[c] = (int32_t)part >= T ? 1 : 0;
+      for (uint32_t k = 4; k < K; ++k) {  // rare: a token repeated 16 times or more
+        uint32_t acc = 0;
+        for (int w = 0; w < 16; ++w) acc += __popc(v[u][w] & planes[k * VW + 16 * j + w]);
+        part += acc << k;
+      }
+      part = group_sum<G>(part);  // the group's partial counts (groups are aligned runs of G lanes)
+      if (j == 0 && c[u] < c1) {
+        if (!ok[u]) {
+          atomicOr(a.status, ST_BAD_BIN);
+        } else {
+          if (a.count_out) a.count_out[c[u]] = (uint16_t)part;
+          if (a.pass_out) a.pass_out[c[u]] = (int32_t)part >= T ? 1 : 0;
+        }
+      }
     }
   }
   wave_sync();
@@ -222,12 +261,14 @@ __device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, ui
 
 template <int VW, int NW, bool PERSISTENT, bool COOP>
 __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
-  constexpr uint32_t kHistWords = VW * 16;
-  constexpr uint32_t kPerWave = kHistWords + kMaxPlanes * VW;
+  // one region per wavefront: the token histogram (4^q uint16 counters),
+  // then, in the same words, the multiplicity planes (kMaxPlanes x VW words)
+  constexpr uint32_t kPerWave = VW * 16;
+  static_assert(kMaxPlanes * VW <= kPerWave, "planes fit the histogram's words");
   __shared__ __attribute__((aligned(16))) uint32_t lds[NW * kPerWave];
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   uint32_t* hist = lds + wave * kPerWave;
-  uint32_t* planes = hist + kHistWords;
+  uint32_t* planes = hist;
   const uint64_t n_reads = a.dyn ? min(a.dyn->n_reads, a.n_reads) : a.n_reads;
   const uint64_t n_cand = a.dyn ? min(a.dyn->n_cand, a.n_cand) : a.n_cand;
   if (a.status[0] & ~(uint32_t)(ST_BAD_BIN | ST_BAD_CAND_OFF)) return;  // rejected reads
@@ -274,11 +315,11 @@ hipError_t launch_nw(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
   return launch_nw_layout<VW, NW, false>(a, cfg, s);
 }
 
-// LDS per wavefront: (16 + kMaxPlanes) * VW words; the wave count per group
-// is capped so a group stays within 64 KB.
+// LDS per wavefront: 16 * VW words; the wave count per group is capped so a
+// group stays within 64 KB.
 template <int VW>
 hipError_t launch_vw(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
-  constexpr int kMaxNW = VW >= 512 ? 1 : (VW >= 128 ? 4 : 8);
+  constexpr int kMaxNW = VW >= 512 ? 2 : 8;
   const int nw = cfg.waves > 0 ? cfg.waves : kMaxNW;
   if (nw >= 8 && kMaxNW >= 8) return launch_nw<VW, (kMaxNW >= 8 ? 8 : 1)>(a, cfg, s);
   if (nw >= 4 && kMaxNW >= 4) return launch_nw<VW, (kMaxNW >= 4 ? 4 : 1)>(a, cfg, s);

@@ -61,7 +61,9 @@ __global__ __launch_bounds__(256) void k_tokenize(TokArgs a) {
   const uint32_t R4 = 1u << (2 * q);
   const uint8_t* rd = a.bases + o0;
   uint32_t* out = a.tokens + token_base(o0, r);
-  const int64_t npad = (ntok + 31) & ~31ll;
+  // pad to the next multiple of 32 strictly above ntok: the scan folds the
+  // last partial block exactly and may read one block past the full ones
+  const int64_t npad = (ntok / 32 + 1) * 32;
   for (int64_t i = lane; i < npad; i += 64) {
     uint32_t code = R4;
     if (i < ntok) {
