@@ -37,6 +37,19 @@ enum : uint32_t {
 };
 int status_to_error(uint32_t st);
 
+// Loads through a global-memory pointer. A pointer that was itself loaded
+// from memory (a request descriptor's token list, say) is a generic pointer
+// to the compiler, which then issues flat loads; those also count against the
+// LDS wait counter, so every wait for an LDS read would wait for them too.
+typedef unsigned int grim_u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ldg4(const uint32_t* p) {
+  const grim_u32x4 v = *(const __attribute__((address_space(1))) grim_u32x4*)(const void*)p;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint32_t ldg1(const uint32_t* p) {
+  return *(const __attribute__((address_space(1))) uint32_t*)(const void*)p;
+}
+
 // Token storage: uint32 per token. Read r's tokens start at
 // token_base(offsets[r], r) (a multiple of 32 tokens) and are padded with the
 // code R4 = 4^q up to the next multiple of 32 above the token count (so at

@@ -23,8 +23,9 @@
 // so the 32 CUs of one XCD work on the tiles of the same read chunk, whose
 // tokens then stay in that XCD's L2.
 //
-// Full 32-token blocks go through the Harley-Seal tree; the remainder of a
-// read is folded exactly as power-of-two parts, so no padding token costs
+// Full 32-token blocks go through the Harley-Seal tree, two blocks per step
+// so that only every other block's carry ripples through the upper planes;
+// the remainder of a read is folded exactly as power-of-two parts, so no padding token costs
 // work unless another read of the wavefront needs that part. Counters have
 // 8 planes (counts up to 255); a wavefront holding a longer read switches to
 // 16 planes and covers its words in 2-word passes, which keeps that path
@@ -125,6 +126,15 @@ __device__ __forceinline__ void add_carry(Counters<LW, NHI>& c, const uint32_t (
   }
 }
 
+// The 32 token offsets of one full block.
+__device__ __forceinline__ void load_block(uint32_t (&tk)[32], const uint32_t* src) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const uint4 v = ldg4(src + 4 * i);
+    tk[4 * i + 0] = v.x; tk[4 * i + 1] = v.y; tk[4 * i + 2] = v.z; tk[4 * i + 3] = v.w;
+  }
+}
+
 // Fold 32 tokens into the counters.
 template <int LW, int NHI>
 __device__ __forceinline__ void fold32(Counters<LW, NHI>& c, const char* lds_lane, const uint32_t (&tk)[32]) {
@@ -141,12 +151,12 @@ __device__ __forceinline__ void load_part(uint32_t (&tk)[N], const uint32_t* src
 #pragma unroll
     for (int i = 0; i < N / 4; ++i) {
       uint4 v = make_uint4(zero_off, zero_off, zero_off, zero_off);
-      if (active) v = reinterpret_cast<const uint4*>(src)[i];
+      if (active) v = ldg4(src + 4 * i);
       tk[4 * i + 0] = v.x; tk[4 * i + 1] = v.y; tk[4 * i + 2] = v.z; tk[4 * i + 3] = v.w;
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < N; ++i) tk[i] = active ? src[i] : zero_off;
+    for (int i = 0; i < N; ++i) tk[i] = active ? ldg1(src + i) : zero_off;
   }
 }
 
@@ -189,16 +199,29 @@ __device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lan
   for (int k = 0; k < NP; ++k)
 #pragma unroll
     for (int j = 0; j < LW; ++j) c.p[k][j] = 0;
-  // full 32-token blocks
   const uint32_t nfull = active ? ntok >> 5 : 0;
-  const uint4* tk4 = reinterpret_cast<const uint4*>(tok);
-  for (uint32_t b = 0; b < nfull; ++b) {
-    uint32_t tk[32];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const uint4 v = tk4[b * 8 + i];
-      tk[4 * i + 0] = v.x; tk[4 * i + 1] = v.y; tk[4 * i + 2] = v.z; tk[4 * i + 3] = v.w;
+  // full 32-token blocks, two at a time: the weight-32 carries of the two
+  // trees meet in one full adder at plane 5, and only its carry ripples on
+  uint32_t b = 0;
+  for (; b + 2 <= nfull; b += 2) {
+    uint32_t c1[LW], c2[LW], c64[LW];
+    {
+      uint32_t tk[32];
+      load_block(tk, tok + b * 32);
+      tree<32, LW, NHI>(c, lds_lane, tk, c1);
     }
+    {
+      uint32_t tk[32];
+      load_block(tk, tok + (b + 1) * 32);
+      tree<32, LW, NHI>(c, lds_lane, tk, c2);
+    }
+#pragma unroll
+    for (int j = 0; j < LW; ++j) CSA(c64[j], c.p[5][j], c.p[5][j], c1[j], c2[j]);
+    add_carry<6, LW, NHI>(c, c64);
+  }
+  if (b < nfull) {
+    uint32_t tk[32];
+    load_block(tk, tok + b * 32);
     fold32<LW, NHI>(c, lds_lane, tk);
   }
   // The last partial block, folded exactly as 16/8/4/2/1-token parts: part
