@@ -76,6 +76,9 @@ def parse():
     p.add_argument("--reads-scale", type=float, default=1.0, help="fraction of the stated read count (testing only)")
     p.add_argument("--genome-len", type=int, default=0, help="override genome length (testing only)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--input-cache", default="",
+                   help="directory where the synthetic seed-hit candidate lists are saved and reused "
+                        "(saves minutes of host work when the same workload is run repeatedly)")
     p.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     p.add_argument("--calib-copy-mb", type=int, default=0,
@@ -118,7 +121,18 @@ def main():
     cand = None
     if w.mode == "candidates":
         t0 = time.time()
-        cand = synth.candidates(ref, rd, w.bin_size, w.cand_cap, w.cand_k)
+        cache = None
+        if args.input_cache:
+            os.makedirs(args.input_cache, exist_ok=True)
+            cache = os.path.join(args.input_cache, f"{w.name}_g{len(ref)}_r{rd.n}_b{w.bin_size}_k{w.cand_k}"
+                                                    f"_cap{w.cand_cap}")
+        if cache and os.path.exists(cache + "_cb.npy"):
+            cand = (np.load(cache + "_co.npy"), np.load(cache + "_cb.npy", mmap_mode="c"))
+        else:
+            cand = synth.candidates(ref, rd, w.bin_size, w.cand_cap, w.cand_k)
+            if cache:
+                np.save(cache + "_co.npy", cand[0])
+                np.save(cache + "_cb.npy", cand[1])
         log(f"{len(cand[1]):,} seed-hit candidates in {time.time() - t0:.1f}s")
 
     stream = torch.cuda.current_stream()

@@ -320,7 +320,9 @@ hipError_t launch_nw(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
 template <int VW>
 hipError_t launch_vw(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
   constexpr int kMaxNW = VW >= 512 ? 2 : 8;
-  const int nw = cfg.waves > 0 ? cfg.waves : kMaxNW;
+  // default: 4 wavefronts per group where the pairs are gathered
+  // cooperatively (measured best at q = 6), else as many as fit
+  const int nw = cfg.waves > 0 ? cfg.waves : (VW >= 32 && VW < 512 && cfg.coop ? 4 : kMaxNW);
   if (nw >= 8 && kMaxNW >= 8) return launch_nw<VW, (kMaxNW >= 8 ? 8 : 1)>(a, cfg, s);
   if (nw >= 4 && kMaxNW >= 4) return launch_nw<VW, (kMaxNW >= 4 ? 4 : 1)>(a, cfg, s);
   if (nw >= 2 && kMaxNW >= 2) return launch_nw<VW, (kMaxNW >= 2 ? 2 : 1)>(a, cfg, s);
