@@ -24,6 +24,10 @@
  *     read length times the error tolerance e.
  *   Section 3, steps 4-5: a candidate location is checked against the bit of
  *     the bin holding its first base.
+ *   Section 1 (seed-and-extend step 5) and Section 5 (evaluation metrics):
+ *     a location that passes the filter is verified by aligning the read to
+ *     the reference there with dynamic programming; a passing location that
+ *     yields no mapping within the error budget counts against the filter.
  *
  * Conventions the paper leaves open (each one is listed with its reading in
  * the design notes; the GPU path implements the same reading independently):
@@ -37,7 +41,13 @@
  *   - every token occurrence of a read counts (repeated tokens add again);
  *   - pass means count >= T; T <= 0 passes every bin;
  *   - E = ceil(e_permille * L / 1000) in integer arithmetic, unless an explicit
- *     per-read E is given.
+ *     per-read E is given;
+ *   - verification of (read, bin x) aligns the whole read against any
+ *     substring of the bases that bin x's tokens cover, [x*B, min(x*B + B + O
+ *     + q - 1, G)), with unit-cost substitutions, insertions and deletions
+ *     (Levenshtein distance, free start and end in the reference); a byte
+ *     other than A, C, G, T (either case) matches nothing; the location maps
+ *     when that distance is at most E.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -198,6 +208,80 @@ int oracle_scan_candidates(const uint8_t* bits, uint64_t nb, uint32_t q, const u
       uint32_t cnt = oracle_count(bits + (uint64_t)x * R, bases + offsets[r], L, q);
       if (counts) counts[k] = (uint16_t)cnt;
       if (pass) pass[k] = (int64_t)cnt >= T ? 1 : 0;
+    }
+  }
+  return bad ? -1 : 0;
+}
+
+/* Smallest edit distance between the whole read and any substring of text:
+ * the textbook dynamic program over one column at a time. Row i of a column
+ * holds the distance of read[0..i) to the best substring ending at that text
+ * position; row 0 is 0 in every column (the substring may start anywhere). */
+uint32_t oracle_semiglobal_distance(const uint8_t* read, uint32_t L, const uint8_t* text, uint64_t n) {
+  uint32_t* col = (uint32_t*)malloc(sizeof(uint32_t) * (L + 1));
+  if (!col) return UINT32_MAX;
+  for (uint32_t i = 0; i <= L; ++i) col[i] = i;  /* empty text prefix */
+  uint32_t best = col[L];
+  for (uint64_t j = 0; j < n; ++j) {
+    const int tc = base_code(text[j]);
+    uint32_t diag = col[0];  /* previous column, row i - 1 */
+    col[0] = 0;
+    for (uint32_t i = 1; i <= L; ++i) {
+      const int rc = base_code(read[i - 1]);
+      const uint32_t sub = diag + ((rc >= 0 && rc == tc) ? 0u : 1u);
+      const uint32_t del = col[i] + 1;       /* text base skipped */
+      const uint32_t ins = col[i - 1] + 1;   /* read base skipped */
+      uint32_t v = sub < del ? sub : del;
+      if (ins < v) v = ins;
+      diag = col[i];
+      col[i] = v;
+    }
+    if (col[L] < best) best = col[L];
+  }
+  free(col);
+  return best;
+}
+
+/* Bases that bin x's tokens cover: [*lo, *hi). */
+void oracle_bin_bases(uint64_t x, uint64_t G, uint32_t B, uint32_t O, uint32_t q, uint64_t* lo, uint64_t* hi) {
+  uint64_t a, b;
+  oracle_bin_extent(x, G, B, O, q, &a, &b);
+  *lo = a;
+  *hi = b > a ? b + q - 1 : a;
+}
+
+/* Verification of listed (read, bin) pairs: dist[k] = semi-global distance of
+ * read r against bin cand_bin[k]'s bases and match[k] = (dist <= E_r). Pairs
+ * with verify_mask[k] == 0 (when a mask is given) are skipped: dist 0xFFFF,
+ * match 0. Distances above 0xFFFE are reported as 0xFFFE. */
+int oracle_verify(const uint8_t* ref, uint64_t G, uint32_t B, uint32_t O, uint32_t q, const uint8_t* bases,
+                  const int64_t* offsets, uint64_t n, const uint16_t* max_edits, const uint16_t* err_pm_per_read,
+                  uint32_t err_permille, const int64_t* cand_off, const int32_t* cand_bin,
+                  const uint8_t* verify_mask, uint16_t* dist, uint8_t* match, int nthreads) {
+  const uint64_t nb = oracle_num_bins(G, B);
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+  for (int64_t r = 0; r < (int64_t)n; ++r) {
+    const uint32_t L = (uint32_t)(offsets[r + 1] - offsets[r]);
+    uint32_t E;
+    if (max_edits) E = max_edits[r];
+    else if (err_pm_per_read) E = oracle_max_edits(L, err_pm_per_read[r]);
+    else E = oracle_max_edits(L, err_permille);
+    for (int64_t k = cand_off[r]; k < cand_off[r + 1]; ++k) {
+      const int32_t x = cand_bin[k];
+      if (x < 0 || (uint64_t)x >= nb) { bad = 1; continue; }
+      if (verify_mask && !verify_mask[k]) {
+        dist[k] = 0xFFFF;
+        match[k] = 0;
+        continue;
+      }
+      uint64_t lo, hi;
+      oracle_bin_bases((uint64_t)x, G, B, O, q, &lo, &hi);
+      uint32_t d = oracle_semiglobal_distance(bases + offsets[r], L, ref + lo, hi - lo);
+      if (d > 0xFFFE) d = 0xFFFE;
+      dist[k] = (uint16_t)d;
+      match[k] = d <= E ? 1 : 0;
     }
   }
   return bad ? -1 : 0;

@@ -11,6 +11,11 @@ follows (arXiv 1708.04329):
   * max_edits          Section 6, read-existence figure caption (ceil of L*e)
   * scan_all           Section 3, steps 1-3 over every bin
   * scan_candidates    Section 3, steps 4-5 (bin of the location's first base)
+  * semiglobal_distance, verify
+                       Section 1, seed-and-extend step 5 (dynamic-programming
+                       alignment of the read at a location) and Section 5,
+                       evaluation metrics (a passing location either yields a
+                       mapping or counts against the filter)
 """
 
 from __future__ import annotations
@@ -72,6 +77,12 @@ def load(path: str = _LIB):
     lib.oracle_scan_all.restype = I
     lib.oracle_scan_candidates.argtypes = [P, U64, U32, P, P, U64, P, P, U32, P, P, P, P, I]
     lib.oracle_scan_candidates.restype = I
+    lib.oracle_semiglobal_distance.argtypes = [P, U32, P, U64]
+    lib.oracle_semiglobal_distance.restype = U32
+    lib.oracle_bin_bases.argtypes = [U64, U64, U32, U32, U32, P, P]
+    lib.oracle_bin_bases.restype = None
+    lib.oracle_verify.argtypes = [P, U64, U32, U32, U32, P, P, U64, P, P, U32, P, P, P, P, P, I]
+    lib.oracle_verify.restype = I
     lib.oracle_threads.argtypes = [I]
     lib.oracle_threads.restype = I
     _cache[path] = lib
@@ -181,6 +192,39 @@ class Oracle:
         if rc != 0:
             raise ValueError("candidate bin out of range")
         return counts, pas
+
+    def semiglobal_distance(self, read: bytes, text: bytes) -> int:
+        """Smallest edit distance of the whole read to any substring of text."""
+        r = _u8(np.frombuffer(bytes(read), np.uint8))
+        t = _u8(np.frombuffer(bytes(text), np.uint8))
+        return int(self.lib.oracle_semiglobal_distance(_p(r), len(r), _p(t), len(t)))
+
+    def bin_bases(self, x: int, G: int, B: int, O: int, q: int):
+        """Bases [lo, hi) covered by the tokens of bin x."""
+        lo, hi = ctypes.c_uint64(), ctypes.c_uint64()
+        self.lib.oracle_bin_bases(x, G, B, O, q, ctypes.byref(lo), ctypes.byref(hi))
+        return lo.value, hi.value
+
+    def verify(self, ref, B: int, O: int, q: int, bases, offsets, cand_off, cand_bin, verify_mask=None,
+               max_edits=None, err_pm_per_read=None, err_permille: int = 0):
+        """(dist uint16 [P], match uint8 [P]) in candidate (CSR) order; pairs whose
+        verify_mask entry is 0 get dist 0xFFFF and match 0."""
+        ref = _u8(ref)
+        bases = _u8(bases)
+        offs = np.ascontiguousarray(offsets, np.int64)
+        co = np.ascontiguousarray(cand_off, np.int64)
+        cb = np.ascontiguousarray(cand_bin, np.int32)
+        vm = None if verify_mask is None else np.ascontiguousarray(verify_mask, np.uint8)
+        n = len(offs) - 1
+        me, ep = self._edits(n, max_edits, err_pm_per_read)
+        P = len(cb)
+        dist = np.empty(P, dtype=np.uint16)
+        match = np.empty(P, dtype=np.uint8)
+        rc = self.lib.oracle_verify(_p(ref), len(ref), B, O, q, _p(bases), _p(offs), n, _p(me), _p(ep),
+                                    err_permille, _p(co), _p(cb), _p(vm), _p(dist), _p(match), self.threads)
+        if rc != 0:
+            raise ValueError("candidate bin out of range")
+        return dist, match
 
     def threads_used(self) -> int:
         return int(self.lib.oracle_threads(self.threads))

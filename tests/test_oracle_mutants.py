@@ -15,6 +15,7 @@ import tempfile
 import pytest
 
 import test_oracle_pins as pins
+import test_oracle_verify_pins as vpins
 from oracle import Oracle
 from oracle.oracle import BUILD_CMD, _SRC
 
@@ -30,6 +31,12 @@ MUTANTS = {
     "last_reference_window_dropped": ("? G - q + 1 : 0", "? G - q : 0"),
     "partial_last_bin_dropped": ("return (G + B - 1) / B;", "return G / B;"),
     "bins_not_extended_at_start": ("uint64_t a = x * (uint64_t)B;", "uint64_t a = x * (uint64_t)B + 1;"),
+    "verify_global_not_semiglobal": ("col[0] = 0;", "col[0] = diag + 1;"),
+    "verify_alignment_must_reach_text_end": ("if (col[L] < best) best = col[L];", ""),
+    "verify_n_matches_n": ("(rc >= 0 && rc == tc)", "(rc == tc)"),
+    "verify_window_misses_last_token_bases": ("*hi = b > a ? b + q - 1 : a;", "*hi = b > a ? b : a;"),
+    "verify_match_strict": ("match[k] = d <= E ? 1 : 0;", "match[k] = d < E ? 1 : 0;"),
+    "verify_substitution_free": ("((rc >= 0 && rc == tc) ? 0u : 1u)", "0u"),
 }
 
 PIN_CALLS = [
@@ -49,6 +56,12 @@ PIN_CALLS = [
     lambda o: pins.test_last_partial_bin_and_tail_token(o),
     lambda o: pins.test_n_windows(o),
     lambda o: pins.test_nonpositive_threshold_passes_everything(o),
+    *[(lambda o, s=s: vpins.test_verify_distance_bruteforce(o, s)) for s in range(4)],
+    lambda o: vpins.test_verify_nonacgt_matches_nothing(o),
+    lambda o: vpins.test_verify_closed_forms(o),
+    lambda o: vpins.test_verify_window_edges(o),
+    lambda o: vpins.test_verify_truth_locations(o),
+    lambda o: vpins.test_verify_mask_skips_pairs(o),
 ]
 
 
