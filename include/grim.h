@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define GRIM_ABI_VERSION 1
+#define GRIM_ABI_VERSION 2
 
 enum grim_status {
   GRIM_OK = 0,
@@ -48,6 +48,7 @@ enum grim_status {
 /* Index layouts (bit flags; one index may hold both). */
 #define GRIM_LAYOUT_TM 1u /* token-major: row t = bit x of every bin x (all-bins scan) */
 #define GRIM_LAYOUT_BM 2u /* bin-major: bin x = its 4^q-bit vector (candidate checks) */
+#define GRIM_LAYOUT_REF 4u /* the reference itself, one base code per byte (verification) */
 
 /* grim_reads.flags */
 #define GRIM_READS_ALLOW_SHORT_OVERLAP 1u /* compute reads with O < L + E - q instead of
@@ -71,6 +72,7 @@ typedef struct {
   uint64_t tm_bytes;     /* device bytes of the token-major layout (0 if absent) */
   uint64_t bm_bytes;     /* device bytes of the bin-major layout (0 if absent) */
   uint64_t bits_bytes;   /* n_bins * 4^q / 8: the existence bits themselves */
+  uint64_t ref_bytes;    /* device bytes of the reference copy (GRIM_LAYOUT_REF; 0 if absent) */
 } grim_index_info_t;
 
 /* A read set. Read r is bases[offsets[r] .. offsets[r+1]) and has length L_r.
@@ -106,7 +108,10 @@ const char* grim_last_error(void);
  * valid token with code t starts at some s with x*B <= s < x*B + B + O and
  * s <= G - q (a token belongs to the bin holding its first base). Token code:
  * A=0, C=1, G=2, T=3, first base most significant. The bits are stored in the
- * layouts `layout` asks for (GRIM_LAYOUT_TM and/or GRIM_LAYOUT_BM).
+ * layouts `layout` asks for (GRIM_LAYOUT_TM and/or GRIM_LAYOUT_BM). With
+ * GRIM_LAYOUT_REF the index also keeps the reference, one byte per base
+ * (0..3 for A, C, G, T in either case, 4 for any other byte), for
+ * grim_verify_candidates.
  *   ref, ref_len   reference bases (host, or device if ref_on_device = 1)
  *   bin_size       B >= 1; overlap O >= 0; q in [1, 7]
  *   out            receives a new handle, resident on the current HIP device
@@ -122,7 +127,8 @@ int grim_index_info(const grim_index* idx, grim_index_info_t* out);
 /* Copy `nbytes` of one stored layout, starting at byte `offset`, to host
  * memory `dst` (for inspection and tests). Token-major bytes are row t of
  * tm_row_words uint32 words, bit (x % 32) of word x / 32 = bin x; bin-major
- * bytes are bin x of bm_vec_words words, bit (t % 32) of word t / 32 = token t.
+ * bytes are bin x of bm_vec_words words, bit (t % 32) of word t / 32 = token t;
+ * reference bytes (GRIM_LAYOUT_REF) are base codes 0..4, one per base.
  * Errors: GRIM_EINVAL (layout absent, range outside it). */
 int grim_index_read(const grim_index* idx, uint32_t layout, uint64_t offset, uint64_t nbytes,
                     void* dst);
@@ -171,6 +177,32 @@ int grim_filter_scan(const grim_index* idx, const grim_reads* reads, uint32_t* m
 int grim_filter_candidates(const grim_index* idx, const grim_reads* reads,
                            const int64_t* cand_off, const int32_t* cand_bin, uint64_t n_cand,
                            uint16_t* count_out, uint8_t* pass_out, void* hip_stream);
+
+/* Verification of listed (read, bin) pairs, the step after the filter: a
+ * location that passes is aligned with dynamic programming (Section 1,
+ * seed-and-extend step 5), and a passing location that yields no mapping
+ * counts against the filter (Section 5, evaluation metrics). For entry k,
+ * read r and bin x = cand_bin[k]:
+ *   dist_out[k]  = the smallest Levenshtein distance (unit-cost substitution,
+ *                  insertion, deletion) between the whole read and any
+ *                  substring of the bases bin x's tokens cover,
+ *                  [x*B, min(x*B + B + O + q - 1, G)); a base other than
+ *                  A, C, G, T (either case), in the read or the reference,
+ *                  matches nothing; values above 0xFFFE read 0xFFFE;
+ *   match_out[k] = dist_out[k] <= E_r (the read's error budget).
+ * Entries with verify_mask[k] == 0 are not aligned: dist 0xFFFF, match 0.
+ * Pass the filter's pass_out as verify_mask to align only passing pairs, or
+ * NULL to align every pair. Needs GRIM_LAYOUT_REF; reads of up to 512
+ * bases.
+ *   cand_off, cand_bin   as for grim_filter_candidates (device)
+ *   verify_mask          device, [n_cand] uint8, or NULL
+ *   dist_out, match_out  device, [n_cand] uint16 and uint8
+ * Errors: GRIM_EINVAL (no reference in the index, a read longer than 512
+ *         bases or shorter than q, bad offsets, bin out of range),
+ *         GRIM_ENOMEM. On error the outputs are unspecified. */
+int grim_verify_candidates(const grim_index* idx, const grim_reads* reads, const int64_t* cand_off,
+                           const int32_t* cand_bin, uint64_t n_cand, const uint8_t* verify_mask,
+                           uint16_t* dist_out, uint8_t* match_out, void* hip_stream);
 
 /* ------------------------------------------------------------------------
  * Batching layer: launch-shape tuning and a graph-captured steady-state loop.
@@ -366,6 +398,7 @@ typedef struct {
   grim_kernel_time scan;        /* all-bins accumulate + threshold */
   grim_kernel_time candidates;  /* candidate checks */
   grim_kernel_time build;       /* index build */
+  grim_kernel_time verify;      /* verification alignments (grim_verify_candidates) */
 } grim_profile_t;
 
 /* Turn event timing of library kernels on (1) or off (0). */

@@ -38,6 +38,7 @@ int status_to_error(uint32_t st) {
   if (st & ST_COUNT_U8) return set_error(GRIM_EINVAL, "uint8 counts need reads of at most 255 tokens");
   if (st & ST_BAD_CAND_OFF) return set_error(GRIM_EINVAL, "candidate offsets out of order or out of range");
   if (st & ST_BAD_BIN) return set_error(GRIM_EINVAL, "a candidate bin is outside [0, n_bins)");
+  if (st & ST_VERIFY_LONG) return set_error(GRIM_EINVAL, "a read to verify is longer than %u bases", kVerifyMaxLen);
   if (st & ST_OVERLAP)
     return set_error(GRIM_EOVERLAP, "a read is not covered by the bin overlap (O < L + E - q)");
   return set_error(GRIM_EINVAL, "invalid input (status 0x%x)", st);
@@ -130,6 +131,10 @@ void free_workspace(grim_workspace& ws) {
   if (ws.staging) (void)hipFree(ws.staging);
   if (ws.order) (void)hipFree(ws.order);
   if (ws.hist) (void)hipFree(ws.hist);
+  if (ws.vbucket) (void)hipFree(ws.vbucket);
+  if (ws.vbucket_host) (void)hipHostFree(ws.vbucket_host);
+  if (ws.vitem_pair) (void)hipFree(ws.vitem_pair);
+  if (ws.vitem_read) (void)hipFree(ws.vitem_read);
   ws = grim_workspace{};
 }
 
@@ -295,12 +300,14 @@ int fill_geometry(grim_index* idx, uint64_t G, uint32_t B, uint32_t O, uint32_t 
   idx->vec_words = idx->R4 >= 32 ? idx->R4 / 32 : 1;
   idx->tm_bytes = (layout & GRIM_LAYOUT_TM) ? (uint64_t)idx->R4 * idx->row_words * 4 : 0;
   idx->bm_bytes = (layout & GRIM_LAYOUT_BM) ? idx->nb * idx->vec_words * 4 : 0;
+  idx->ref_bytes = (layout & GRIM_LAYOUT_REF) ? G : 0;
   return GRIM_OK;
 }
 
 int alloc_layouts(grim_index* idx) {
   if (idx->tm_bytes) GRIM_HIP_TRY(hipMalloc(&idx->tm, idx->tm_bytes));
   if (idx->bm_bytes) GRIM_HIP_TRY(hipMalloc(&idx->bm, idx->bm_bytes));
+  if (idx->ref_bytes) GRIM_HIP_TRY(hipMalloc(&idx->ref, idx->ref_bytes));
   return GRIM_OK;
 }
 
@@ -309,6 +316,7 @@ void destroy(grim_index* idx) {
   DeviceGuard dg(idx->device);
   if (idx->tm) (void)hipFree(idx->tm);
   if (idx->bm) (void)hipFree(idx->bm);
+  if (idx->ref) (void)hipFree(idx->ref);
   free_workspace(idx->ws);
   delete idx;
 }
@@ -336,6 +344,7 @@ int grim_profile_read(grim_profile_t* out, int reset) {
   out->scan = g_prof[PROF_SCAN];
   out->candidates = g_prof[PROF_CAND];
   out->build = g_prof[PROF_BUILD];
+  out->verify = g_prof[PROF_VERIFY];
   if (reset)
     for (auto& k : g_prof) k = grim_kernel_time{0, 0.0, 0.0};
   return GRIM_OK;
@@ -350,8 +359,8 @@ int grim_build_index(const uint8_t* ref, uint64_t ref_len, uint32_t ref_on_devic
   if (bin_size == 0) return set_error(GRIM_EINVAL, "bin_size must be >= 1");
   if (q < 1 || q > 7) return set_error(GRIM_EINVAL, "q must be in [1, 7]");
   if (ref_len < q) return set_error(GRIM_EINVAL, "reference shorter than q");
-  if (layout == 0 || (layout & ~(GRIM_LAYOUT_TM | GRIM_LAYOUT_BM)))
-    return set_error(GRIM_EINVAL, "layout must be GRIM_LAYOUT_TM and/or GRIM_LAYOUT_BM");
+  if (layout == 0 || (layout & ~(GRIM_LAYOUT_TM | GRIM_LAYOUT_BM | GRIM_LAYOUT_REF)))
+    return set_error(GRIM_EINVAL, "layout must be a combination of GRIM_LAYOUT_TM, GRIM_LAYOUT_BM, GRIM_LAYOUT_REF");
   if (ref_on_device > 1) return set_error(GRIM_EINVAL, "ref_on_device must be 0 or 1");
   if ((ref_len + bin_size - 1) / bin_size > (1ull << 31)) return set_error(GRIM_EINVAL, "more than 2^31 bins");
   int dev = 0;
@@ -392,6 +401,7 @@ int grim_build_index(const uint8_t* ref, uint64_t ref_len, uint32_t ref_on_devic
     ps.start(s);
     if (idx->tm) e = launch_build_tm(a, s);
     if (e == hipSuccess && idx->bm) e = launch_build_bm(a, s);
+    if (e == hipSuccess && idx->ref) e = launch_ref_codes(dref, ref_len, idx->ref, s);
     ps.stop(s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     ps.collect();
@@ -419,6 +429,7 @@ int grim_index_info(const grim_index* idx, grim_index_info_t* out) {
   out->tm_bytes = idx->tm_bytes;
   out->bm_bytes = idx->bm_bytes;
   out->bits_bytes = idx->nb * (uint64_t)idx->R4 / 8;
+  out->ref_bytes = idx->ref_bytes;
   return GRIM_OK;
 }
 
@@ -429,7 +440,8 @@ int grim_index_read(const grim_index* idx, uint32_t layout, uint64_t offset, uin
   uint64_t size = 0;
   if (layout == GRIM_LAYOUT_TM) { src = idx->tm; size = idx->tm_bytes; }
   else if (layout == GRIM_LAYOUT_BM) { src = idx->bm; size = idx->bm_bytes; }
-  else return set_error(GRIM_EINVAL, "layout must be exactly one of GRIM_LAYOUT_TM, GRIM_LAYOUT_BM");
+  else if (layout == GRIM_LAYOUT_REF) { src = idx->ref; size = idx->ref_bytes; }
+  else return set_error(GRIM_EINVAL, "layout must be exactly one of GRIM_LAYOUT_TM, GRIM_LAYOUT_BM, GRIM_LAYOUT_REF");
   if (!src) return set_error(GRIM_EINVAL, "layout not present in this index");
   if (offset > size || nbytes > size - offset) return set_error(GRIM_EINVAL, "range outside the layout");
   DeviceGuard dg(idx->device);
@@ -441,10 +453,13 @@ int grim_index_save(const grim_index* idx, const char* path) {
   clear_error();
   if (!idx || !path) return set_error(GRIM_EINVAL, "NULL argument");
   DeviceGuard dg(idx->device);
-  std::vector<uint8_t> payload(idx->tm_bytes + idx->bm_bytes);
+  std::vector<uint8_t> payload(idx->tm_bytes + idx->bm_bytes + idx->ref_bytes);
   if (idx->tm_bytes) GRIM_HIP_TRY(hipMemcpy(payload.data(), idx->tm, idx->tm_bytes, hipMemcpyDeviceToHost));
   if (idx->bm_bytes)
     GRIM_HIP_TRY(hipMemcpy(payload.data() + idx->tm_bytes, idx->bm, idx->bm_bytes, hipMemcpyDeviceToHost));
+  if (idx->ref_bytes)
+    GRIM_HIP_TRY(hipMemcpy(payload.data() + idx->tm_bytes + idx->bm_bytes, idx->ref, idx->ref_bytes,
+                           hipMemcpyDeviceToHost));
   FileHeader h{};
   std::memcpy(h.magic, kMagic, 8);
   h.version = kFileVersion;
@@ -487,7 +502,7 @@ int grim_index_load(const char* path, void* hip_stream, grim_index** out) {
   }
   grim_index probe;
   if (h.B == 0 || h.q < 1 || h.q > 7 || h.G < h.q || h.layout == 0 ||
-      (h.layout & ~(GRIM_LAYOUT_TM | GRIM_LAYOUT_BM))) {
+      (h.layout & ~(GRIM_LAYOUT_TM | GRIM_LAYOUT_BM | GRIM_LAYOUT_REF))) {
     std::fclose(f);
     return set_error(GRIM_EIO, "%s: bad parameters in header", path);
   }
@@ -497,7 +512,7 @@ int grim_index_load(const char* path, void* hip_stream, grim_index** out) {
     std::fclose(f);
     return set_error(GRIM_EIO, "%s: header geometry is inconsistent", path);
   }
-  std::vector<uint8_t> payload(h.tm_bytes + h.bm_bytes);
+  std::vector<uint8_t> payload(h.tm_bytes + h.bm_bytes + probe.ref_bytes);
   const bool ok = payload.empty() || std::fread(payload.data(), payload.size(), 1, f) == 1;
   std::fclose(f);
   if (!ok) return set_error(GRIM_EIO, "%s: truncated payload", path);
@@ -516,6 +531,9 @@ int grim_index_load(const char* path, void* hip_stream, grim_index** out) {
   if (idx->tm_bytes) GRIM_HIP_TRY(hipMemcpyAsync(idx->tm, payload.data(), idx->tm_bytes, hipMemcpyHostToDevice, s));
   if (idx->bm_bytes)
     GRIM_HIP_TRY(hipMemcpyAsync(idx->bm, payload.data() + idx->tm_bytes, idx->bm_bytes, hipMemcpyHostToDevice, s));
+  if (idx->ref_bytes)
+    GRIM_HIP_TRY(hipMemcpyAsync(idx->ref, payload.data() + idx->tm_bytes + idx->bm_bytes, idx->ref_bytes,
+                                hipMemcpyHostToDevice, s));
   GRIM_HIP_TRY(hipStreamSynchronize(s));
   *out = idx.release();
   return GRIM_OK;
@@ -624,6 +642,83 @@ int grim_filter_candidates(const grim_index* cidx, const grim_reads* rd, const i
   rc = finish_status(idx, s);
   pt.collect();
   ps.collect();
+  return rc;
+}
+
+int grim_verify_candidates(const grim_index* cidx, const grim_reads* rd, const int64_t* cand_off,
+                           const int32_t* cand_bin, uint64_t n_cand, const uint8_t* verify_mask, uint16_t* dist_out,
+                           uint8_t* match_out, void* hip_stream) {
+  clear_error();
+  int rc = check_reads_args(cidx, rd);
+  if (rc) return rc;
+  grim_index* idx = const_cast<grim_index*>(cidx);
+  if (!(idx->layout & GRIM_LAYOUT_REF) || !idx->ref)
+    return set_error(GRIM_EINVAL, "index has no reference copy (build it with GRIM_LAYOUT_REF)");
+  if (rd->n_reads && !cand_off) return set_error(GRIM_EINVAL, "cand_off is NULL");
+  if (n_cand && (!cand_bin || !dist_out || !match_out))
+    return set_error(GRIM_EINVAL, "cand_bin, dist_out and match_out must not be NULL");
+  if (rd->n_reads == 0 || n_cand == 0) return GRIM_OK;
+  std::lock_guard<std::mutex> lk(idx->mu);
+  DeviceGuard dg(idx->device);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  ReadView v;
+  rc = stage_reads(idx, rd, s, &v);
+  if (rc) return rc;
+  ProfSpan pt(PROF_TOKENIZE);
+  rc = tokenize_reads(idx, rd, v, 65535u, 0u, s, pt);  // length checks and thresholds
+  if (rc) return rc;
+  grim_workspace& ws = idx->ws;
+  if (!ws.vbucket) GRIM_HIP_TRY(hipMalloc(&ws.vbucket, kVerifyBuckets * sizeof(uint64_t)));
+  if (!ws.vbucket_host)
+    GRIM_HIP_TRY(hipHostMalloc(&ws.vbucket_host, 2 * kVerifyBuckets * sizeof(uint64_t), hipHostMallocDefault));
+  GRIM_HIP_TRY(launch_zero_words(reinterpret_cast<uint32_t*>(ws.vbucket), 2 * kVerifyBuckets, s));
+  VerifyArgs a{};
+  a.ref = idx->ref;
+  a.G = idx->G;
+  a.B = idx->B;
+  a.O = idx->O;
+  a.q = idx->q;
+  a.nb = idx->nb;
+  a.bases = v.bases;
+  a.offsets = v.offsets;
+  a.thr = ws.thr;
+  a.n_reads = rd->n_reads;
+  a.cand_off = cand_off;
+  a.cand_bin = cand_bin;
+  a.n_cand = n_cand;
+  a.verify_mask = verify_mask;
+  a.dist_out = dist_out;
+  a.match_out = match_out;
+  a.status = ws.status;
+  a.bucket = ws.vbucket;
+  GRIM_HIP_TRY(launch_verify_count(a, s));
+  // pairs per length class, and the status of the inputs
+  uint64_t* counts = ws.vbucket_host;
+  uint64_t* first = ws.vbucket_host + kVerifyBuckets;
+  GRIM_HIP_TRY(hipMemcpyAsync(counts, ws.vbucket, kVerifyBuckets * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  rc = finish_status(idx, s);
+  pt.collect();
+  if (rc) return rc;
+  uint64_t total = 0;
+  for (uint32_t w = 0; w < kVerifyBuckets; ++w) {
+    first[w] = total;
+    total += counts[w];
+  }
+  if (total == 0) return GRIM_OK;
+  rc = grow(&ws.vitem_pair, &ws.vitem_cap, total);
+  if (rc) return rc;
+  rc = grow(&ws.vitem_read, &ws.vitem_read_cap, total);
+  if (rc) return rc;
+  a.item_pair = ws.vitem_pair;
+  a.item_read = ws.vitem_read;
+  GRIM_HIP_TRY(hipMemcpyAsync(ws.vbucket, first, kVerifyBuckets * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  GRIM_HIP_TRY(launch_verify_scatter(a, s));
+  ProfSpan pv(PROF_VERIFY);
+  pv.start(s);
+  for (uint32_t w = 1; w < kVerifyBuckets; ++w) GRIM_HIP_TRY(launch_verify_align(a, w, first[w], counts[w], s));
+  pv.stop(s);
+  rc = finish_status(idx, s);
+  pv.collect();
   return rc;
 }
 

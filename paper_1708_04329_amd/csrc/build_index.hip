@@ -14,6 +14,8 @@
 // atomic ORs while walking the positions whose tokens can reach the tile,
 // then writes the tile out with coalesced stores.
 
+#include <algorithm>
+
 #include "grim_internal.h"
 
 namespace grim {
@@ -152,6 +154,31 @@ hipError_t launch_build_bm(const BuildArgs& a, hipStream_t s) {
     case 512: hipLaunchKernelGGL(k_build_bm<512>, dim3((unsigned)blocks), dim3(1024), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// Reference copy for verification: one base code per byte (grid-stride loop,
+// the reference is read once, coalesced).
+__global__ __launch_bounds__(256) void k_ref_codes(const uint8_t* ref, uint64_t G, uint8_t* codes) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G; i += stride) {
+    const uint8_t c = ref[i];
+    uint8_t v = 4;
+    switch (c | 0x20) {  // ASCII letters: fold to lower case
+      case 'a': v = 0; break;
+      case 'c': v = 1; break;
+      case 'g': v = 2; break;
+      case 't': v = 3; break;
+      default: break;
+    }
+    codes[i] = v;
+  }
+}
+
+hipError_t launch_ref_codes(const uint8_t* ref, uint64_t G, uint8_t* codes, hipStream_t s) {
+  if (G == 0) return hipSuccess;
+  const uint64_t blocks = std::min<uint64_t>((G + 255) / 256, 256ull * 64);
+  hipLaunchKernelGGL(k_ref_codes, dim3((unsigned)blocks), dim3(256), 0, s, ref, G, codes);
   return hipGetLastError();
 }
 

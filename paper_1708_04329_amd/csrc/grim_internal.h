@@ -34,6 +34,7 @@ enum : uint32_t {
   ST_TOO_LONG = 8u,        // more than 65535 tokens in a read
   ST_BAD_BIN = 16u,        // candidate bin outside [0, n_bins)
   ST_BAD_CAND_OFF = 32u,   // candidate offsets out of order / out of range
+  ST_VERIFY_LONG = 64u,    // a read to verify has more than kVerifyMaxLen bases
 };
 int status_to_error(uint32_t st);
 
@@ -112,6 +113,41 @@ struct BuildArgs {
 };
 hipError_t launch_build_tm(const BuildArgs& a, hipStream_t s);
 hipError_t launch_build_bm(const BuildArgs& a, hipStream_t s);
+// Reference bytes -> base codes (0..3 for ACGT in either case, 4 otherwise).
+hipError_t launch_ref_codes(const uint8_t* ref, uint64_t G, uint8_t* codes, hipStream_t s);
+
+// Verification of (read, bin) pairs: bit-parallel semi-global edit distance
+// of the read against the bases of the bin's extent.
+constexpr uint32_t kVerifyMaxLen = 512;   // bases per read: 16 words of 32 rows
+constexpr uint32_t kVerifyBuckets = 17;   // work lists by words per read, 1..16
+struct VerifyArgs {
+  const uint8_t* ref;        // base codes, G bytes
+  uint64_t G;
+  uint32_t B, O, q;
+  uint64_t nb;
+  const uint8_t* bases;      // reads, ASCII
+  const int64_t* offsets;
+  const int32_t* thr;        // T_r (E_r is recovered as (L - q + 1 - T_r) / q)
+  uint64_t n_reads;
+  const int64_t* cand_off;
+  const int32_t* cand_bin;
+  uint64_t n_cand;
+  const uint8_t* verify_mask;  // or null: every pair
+  uint16_t* dist_out;
+  uint8_t* match_out;
+  uint32_t* status;
+  uint64_t* bucket;          // [kVerifyBuckets] counts, then cursors
+  uint64_t* item_pair;       // work list: pair index
+  uint32_t* item_read;       //            and its read
+};
+// Count the pairs to align per bucket (and write the outputs of skipped pairs).
+hipError_t launch_verify_count(const VerifyArgs& a, hipStream_t s);
+// Fill the work lists; a.bucket holds each bucket's first slot on entry.
+hipError_t launch_verify_scatter(const VerifyArgs& a, hipStream_t s);
+// Align work items [first, first + count), all of whose reads have `words`
+// 32-base words.
+hipError_t launch_verify_align(const VerifyArgs& a, uint32_t words, uint64_t first, uint64_t count,
+                               hipStream_t s);
 
 // Per-read descriptor for scans over reads scattered across buffers (served
 // requests): token list, output row and threshold of one read.
@@ -195,7 +231,7 @@ hipError_t launch_zero_words(uint32_t* p, uint32_t n, hipStream_t s);
 // ---------------------------------------------------------------------------
 // Profiling: HIP events around kernels, on the stream they run on.
 // ---------------------------------------------------------------------------
-enum ProfKind { PROF_TOKENIZE = 0, PROF_SCAN = 1, PROF_CAND = 2, PROF_BUILD = 3, PROF_N = 4 };
+enum ProfKind { PROF_TOKENIZE = 0, PROF_SCAN = 1, PROF_CAND = 2, PROF_BUILD = 3, PROF_VERIFY = 4, PROF_N = 5 };
 bool profiling();
 struct ProfSpan {
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -227,6 +263,11 @@ struct grim_workspace {
   uint32_t* order = nullptr;       // scan order (reads sorted by length)
   uint64_t order_cap = 0;
   uint32_t* hist = nullptr;        // 64 words of sort scratch
+  uint64_t* vbucket = nullptr;       // device [kVerifyBuckets] verification counts / cursors
+  uint64_t* vbucket_host = nullptr;  // pinned [2 * kVerifyBuckets]: counts, first slots
+  uint64_t* vitem_pair = nullptr;    // verification work list
+  uint32_t* vitem_read = nullptr;
+  uint64_t vitem_cap = 0, vitem_read_cap = 0;
 };
 
 struct grim_index {
@@ -240,7 +281,8 @@ struct grim_index {
   uint32_t R4 = 0, vec_words = 0;
   uint32_t* tm = nullptr;
   uint32_t* bm = nullptr;
-  uint64_t tm_bytes = 0, bm_bytes = 0;
+  uint8_t* ref = nullptr;      // base codes (GRIM_LAYOUT_REF)
+  uint64_t tm_bytes = 0, bm_bytes = 0, ref_bytes = 0;
   std::mutex mu;  // guards ws for the duration of a call
   grim_workspace ws;
 };

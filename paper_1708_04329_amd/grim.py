@@ -31,6 +31,7 @@ GRIM_EIO = -8
 
 LAYOUT_TM = 1
 LAYOUT_BM = 2
+LAYOUT_REF = 4
 READS_ALLOW_SHORT_OVERLAP = 1
 MODE_SCAN = 1
 MODE_CANDIDATES = 2
@@ -53,7 +54,7 @@ class IndexInfo(ctypes.Structure):
                 ("q", ctypes.c_uint32), ("layout", ctypes.c_uint32), ("n_bins", ctypes.c_uint64),
                 ("mask_words", ctypes.c_uint64), ("tm_row_words", ctypes.c_uint64),
                 ("bm_vec_words", ctypes.c_uint32), ("device", ctypes.c_int32), ("tm_bytes", ctypes.c_uint64),
-                ("bm_bytes", ctypes.c_uint64), ("bits_bytes", ctypes.c_uint64)]
+                ("bm_bytes", ctypes.c_uint64), ("bits_bytes", ctypes.c_uint64), ("ref_bytes", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -118,7 +119,8 @@ class KernelTime(ctypes.Structure):
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("tokenize", KernelTime), ("scan", KernelTime), ("candidates", KernelTime), ("build", KernelTime)]
+    _fields_ = [("tokenize", KernelTime), ("scan", KernelTime), ("candidates", KernelTime), ("build", KernelTime),
+                ("verify", KernelTime)]
 
 
 EXPORTS = ["grim_abi_version", "grim_last_error", "grim_build_index", "grim_index_info", "grim_index_read",
@@ -127,7 +129,7 @@ EXPORTS = ["grim_abi_version", "grim_last_error", "grim_build_index", "grim_inde
            "grim_index_set_config", "grim_batcher_create", "grim_batcher_buffers", "grim_batcher_submit",
            "grim_batcher_wait", "grim_batcher_stream", "grim_batcher_free", "grim_serve_create",
            "grim_serve_submit", "grim_serve_poll", "grim_serve_wait", "grim_serve_release", "grim_serve_cancel",
-           "grim_serve_stats", "grim_serve_reset_stats", "grim_serve_destroy"]
+           "grim_serve_stats", "grim_serve_reset_stats", "grim_serve_destroy", "grim_verify_candidates"]
 
 _lib = None
 
@@ -153,6 +155,7 @@ def lib(path: str = LIB_PATH):
         "grim_index_free": ([P], None),
         "grim_filter_scan": ([P, ctypes.POINTER(_Reads), P, P, U32, P], I),
         "grim_filter_candidates": ([P, ctypes.POINTER(_Reads), P, P, U64, P, P, P], I),
+        "grim_verify_candidates": ([P, ctypes.POINTER(_Reads), P, P, U64, P, P, P, P], I),
         "grim_profile_enable": ([I], I),
         "grim_profile_read": ([ctypes.POINTER(Profile), I], I),
         "grim_tune": ([P, ctypes.POINTER(_Reads), P, P, U64, P, ctypes.POINTER(TuneResult)], I),
@@ -298,7 +301,7 @@ class Index:
 
     def read(self, layout: int, offset: int = 0, nbytes: Optional[int] = None) -> np.ndarray:
         inf = self.info()
-        size = inf["tm_bytes"] if layout == LAYOUT_TM else inf["bm_bytes"]
+        size = {LAYOUT_TM: inf["tm_bytes"], LAYOUT_BM: inf["bm_bytes"], LAYOUT_REF: inf["ref_bytes"]}.get(layout, 0)
         nbytes = size - offset if nbytes is None else nbytes
         out = np.empty(nbytes, dtype=np.uint8)
         _check(lib().grim_index_read(self._h, layout, offset, nbytes, out.ctypes.data))
@@ -356,6 +359,21 @@ def grim_filter_candidates(index: Index, reads: ReadSet, cand_off, cand_bin, cou
     r = reads._struct()
     _check(lib().grim_filter_candidates(index.handle, ctypes.byref(r), _ptr(cand_off), _ptr(cand_bin),
                                         len(cand_bin), _ptr(count_out), _ptr(pass_out),
+                                        _stream_handle(stream)))
+
+
+def grim_verify_candidates(index: Index, reads: ReadSet, cand_off, cand_bin, verify_mask=None, dist_out=None,
+                           match_out=None, stream=None):
+    """Verification: dist [P] uint16 (semi-global edit distance against the bin's bases, 0xFFFF
+    where verify_mask is 0) and match [P] uint8 (dist <= E_r) for each listed (read, bin)."""
+    _check_dtype(cand_off, "cand_off", np.int64)
+    _check_dtype(cand_bin, "cand_bin", np.int32)
+    _check_dtype(verify_mask, "verify_mask", np.uint8)
+    _check_dtype(dist_out, "dist_out", np.uint16)
+    _check_dtype(match_out, "match_out", np.uint8)
+    r = reads._struct()
+    _check(lib().grim_verify_candidates(index.handle, ctypes.byref(r), _ptr(cand_off), _ptr(cand_bin),
+                                        len(cand_bin), _ptr(verify_mask), _ptr(dist_out), _ptr(match_out),
                                         _stream_handle(stream)))
 
 

@@ -26,7 +26,7 @@ def declared_functions():
 
 def test_library_loads():
     L = grim.lib()
-    assert L.grim_abi_version() == 1
+    assert L.grim_abi_version() == 2
 
 
 def test_every_declared_symbol_is_exported():
@@ -50,7 +50,7 @@ def test_struct_layouts_match_header():
 #include "grim.h"
 int main(void){
  printf("%zu %zu %zu %zu\n", sizeof(grim_index_info_t), sizeof(grim_reads), sizeof(grim_profile_t), sizeof(grim_kernel_time));
- printf("%zu %zu %zu %zu\n", offsetof(grim_reads, err_permille_all), offsetof(grim_reads, flags), offsetof(grim_index_info_t, device), offsetof(grim_index_info_t, bits_bytes));
+ printf("%zu %zu %zu %zu %zu\n", offsetof(grim_reads, err_permille_all), offsetof(grim_reads, flags), offsetof(grim_index_info_t, device), offsetof(grim_index_info_t, bits_bytes), offsetof(grim_index_info_t, ref_bytes));
  return 0; }
 """
     with tempfile.TemporaryDirectory() as d:
@@ -64,7 +64,7 @@ int main(void){
     assert sizes == [ctypes.sizeof(grim.IndexInfo), ctypes.sizeof(grim._Reads), ctypes.sizeof(grim.Profile),
                      ctypes.sizeof(grim.KernelTime)]
     assert offs == [grim._Reads.err_permille_all.offset, grim._Reads.flags.offset, grim.IndexInfo.device.offset,
-                    grim.IndexInfo.bits_bytes.offset]
+                    grim.IndexInfo.bits_bytes.offset, grim.IndexInfo.ref_bytes.offset]
 
 
 def _err(rc):
@@ -79,7 +79,7 @@ def test_build_rejects_bad_arguments_before_device():
     assert _err(L.grim_build_index(ref, 16, 0, 4, 0, 8, 1, None, ctypes.byref(h)))[0] == grim.GRIM_EINVAL  # q = 8
     assert _err(L.grim_build_index(ref, 16, 0, 0, 0, 4, 1, None, ctypes.byref(h)))[0] == grim.GRIM_EINVAL  # B = 0
     assert _err(L.grim_build_index(ref, 16, 0, 4, 0, 4, 0, None, ctypes.byref(h)))[0] == grim.GRIM_EINVAL  # layout
-    assert _err(L.grim_build_index(ref, 16, 0, 4, 0, 4, 4, None, ctypes.byref(h)))[0] == grim.GRIM_EINVAL
+    assert _err(L.grim_build_index(ref, 16, 0, 4, 0, 4, 8, None, ctypes.byref(h)))[0] == grim.GRIM_EINVAL
     assert _err(L.grim_build_index(ref, 3, 0, 4, 0, 4, 1, None, ctypes.byref(h)))[0] == grim.GRIM_EINVAL   # G < q
     assert _err(L.grim_build_index(None, 16, 0, 4, 0, 4, 1, None, ctypes.byref(h)))[0] == grim.GRIM_EINVAL
     rc, msg = _err(L.grim_build_index(ref, 16, 0, 4, 0, 4, 1, None, None))
@@ -91,6 +91,7 @@ def test_scan_rejects_null_arguments():
     r = grim._Reads()
     assert L.grim_filter_scan(None, ctypes.byref(r), None, None, 0, None) == grim.GRIM_EINVAL
     assert L.grim_filter_candidates(None, ctypes.byref(r), None, None, 0, None, None, None) == grim.GRIM_EINVAL
+    assert L.grim_verify_candidates(None, ctypes.byref(r), None, None, 0, None, None, None, None) == grim.GRIM_EINVAL
     assert L.grim_index_info(None, None) == grim.GRIM_EINVAL
     assert L.grim_index_read(None, 1, 0, 0, None) == grim.GRIM_EINVAL
     L.grim_index_free(None)   # ignored

@@ -319,13 +319,14 @@ def test_save_load_roundtrip(tmp_path):
     import torch
     rng = random.Random(6)
     ref = rand_ref(rng, 50000)
-    idx = build(ref, 80, 100, 5)
+    idx = build(ref, 80, 100, 5, grim.LAYOUT_TM | grim.LAYOUT_BM | grim.LAYOUT_REF)
     p = str(tmp_path / "i.grim")
     idx.save(p)
     idx2 = grim.grim_index_load(p)
-    assert idx2.info() == idx.info()
+    assert idx2.info() == idx.info() and idx.info()["ref_bytes"] == len(ref)
     assert np.array_equal(idx2.read(grim.LAYOUT_TM), idx.read(grim.LAYOUT_TM))
     assert np.array_equal(idx2.read(grim.LAYOUT_BM), idx.read(grim.LAYOUT_BM))
+    assert np.array_equal(idx2.read(grim.LAYOUT_REF), idx.read(grim.LAYOUT_REF))
     raw = bytearray(open(p, "rb").read())
     raw[-5] ^= 0xFF
     bad = str(tmp_path / "bad.grim")

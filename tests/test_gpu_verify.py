@@ -1,0 +1,179 @@
+"""Verification on the GPU (through the C ABI) against the oracle's dynamic
+program, element by element: distances and match flags are integers, so the
+bar is bit-exact. Reads cross every 32-base word boundary up to the 512-base
+limit; bins include the partial last bin; references carry N runs and lower
+case; pairs are selected by a mask, by the filter's pass flags, or all."""
+
+from __future__ import annotations
+
+import random
+
+import numpy as np
+import pytest
+
+import synth
+import synth.configs as C
+from gpu_util import dev, empty, host, log
+from paper_1708_04329_amd import grim
+
+pytestmark = pytest.mark.gpu
+
+
+def rand_ref(rng: random.Random, G: int) -> np.ndarray:
+    ref = bytearray(rng.choice(b"ACGT") for _ in range(G))
+    for _ in range(6):
+        p = rng.randrange(G)
+        ref[p:p + 4] = b"NNNN"[:len(ref[p:p + 4])]
+    for _ in range(6):
+        p = rng.randrange(G)
+        ref[p:p + 80] = bytes(ref[p:p + 80]).lower()
+    return np.frombuffer(bytes(ref[:G]), np.uint8).copy()
+
+
+def mutate(rng: random.Random, s: bytes, k: int) -> bytes:
+    b = bytearray(s)
+    for _ in range(k):
+        op = rng.random()
+        p = rng.randrange(len(b))
+        if op < 0.6:
+            b[p] = rng.choice(b"ACGTN")
+        elif op < 0.8:
+            b.insert(p, rng.choice(b"ACGT"))
+        elif len(b) > 1:
+            del b[p]
+    return bytes(b)
+
+
+def run_verify(idx, rd, co, cb, mask=None, **edits):
+    import torch
+    P = max(1, len(cb))
+    dist = empty((P,), torch.uint16)
+    match = empty((P,), torch.uint8)
+    me, ep = edits.get("max_edits"), edits.get("err_permille")
+    rs = grim.ReadSet(dev(rd.bases), dev(rd.offsets), max_edits=None if me is None else dev(me),
+                      err_permille=None if ep is None else dev(ep), allow_short_overlap=True)
+    grim.grim_verify_candidates(idx, rs, dev(co), dev(cb), None if mask is None else dev(mask), dist, match)
+    torch.cuda.synchronize()
+    return host(dist.view(torch.int16)).view(np.uint16)[:len(cb)], host(match)[:len(cb)]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_verify_matches_oracle_random(oracle, seed):
+    rng = random.Random(700 + seed)
+    G, B, O, q = 120_000, 1000 if seed == 0 else 777, 120, 5
+    ref = rand_ref(rng, G)
+    lengths = [5, 17, 31, 32, 33, 63, 64, 65, 96, 100, 127, 128, 129, 150, 200, 250, 255, 256, 257, 300,
+               383, 384, 385, 448, 511, 512]
+    seqs, truth = [], []
+    for i in range(160):
+        L = lengths[i % len(lengths)]
+        p = rng.randrange(0, G - L)
+        src = ref[p:p + L].tobytes()
+        seqs.append(mutate(rng, src, rng.randrange(0, 6)) if rng.random() < 0.9 else
+                    bytes(rng.choice(b"ACGT") for _ in range(L)))
+        truth.append(p // B)
+    seqs = [s if len(s) >= q else s + b"ACGTA" for s in seqs]
+    seqs = [s[:512] for s in seqs]
+    rd = synth.reads_from_strings(seqs)
+    nb = -(-G // B)
+    cand = []
+    for r in range(rd.n):
+        bins = {truth[r], max(0, truth[r] - 1), nb - 1, rng.randrange(nb)}
+        cand.append(sorted(bins))
+    co = np.zeros(rd.n + 1, np.int64)
+    co[1:] = np.cumsum([len(c) for c in cand])
+    cb = np.concatenate([np.array(c, np.int32) for c in cand])
+    idx = grim.grim_build_index(dev(ref), B, O, q, grim.LAYOUT_BM | grim.LAYOUT_REF)
+    E = np.array([rng.randrange(0, 12) for _ in range(rd.n)], np.uint16)
+    got_d, got_m = run_verify(idx, rd, co, cb, max_edits=E)
+    want_d, want_m = oracle.verify(ref, B, O, q, rd.bases, rd.offsets, co, cb, max_edits=E)
+    bad = np.nonzero(got_d != want_d)[0]
+    assert len(bad) == 0, [(int(k), int(got_d[k]), int(want_d[k])) for k in bad[:8]]
+    assert np.array_equal(got_m, want_m)
+    assert want_m.any() and not want_m.all()
+    # a mask selects pairs; the rest read 0xFFFF / 0
+    mask = np.array([rng.random() < 0.5 for _ in range(len(cb))], np.uint8)
+    got_d, got_m = run_verify(idx, rd, co, cb, mask=mask, max_edits=E)
+    want_d, want_m = oracle.verify(ref, B, O, q, rd.bases, rd.offsets, co, cb, verify_mask=mask, max_edits=E)
+    assert np.array_equal(got_d, want_d) and np.array_equal(got_m, want_m)
+    assert (got_d[mask == 0] == 0xFFFF).all()
+
+
+def test_verify_short_reference_and_edges(oracle):
+    """Texts shorter than the read (last bin), a one-bin reference, reads of q bases."""
+    rng = random.Random(3)
+    for G, B, O, q in [(300, 128, 20, 4), (64, 100, 0, 3), (5000, 64, 16, 6)]:
+        ref = rand_ref(rng, G)
+        seqs = [ref[max(0, G - 40):G].tobytes(), ref[:q].tobytes(), ref[G // 2:G // 2 + 70].tobytes(),
+                bytes(rng.choice(b"ACGT") for _ in range(200))]
+        rd = synth.reads_from_strings(seqs)
+        nb = -(-G // B)
+        co = np.arange(0, 3 * rd.n + 1, 3, dtype=np.int64)
+        cb = np.array([[nb - 1, 0, (nb - 1) // 2] for _ in range(rd.n)], np.int32).reshape(-1)
+        idx = grim.grim_build_index(dev(ref), B, O, q, grim.LAYOUT_TM | grim.LAYOUT_REF)
+        E = np.full(rd.n, 3, np.uint16)
+        got = run_verify(idx, rd, co, cb, max_edits=E)
+        want = oracle.verify(ref, B, O, q, rd.bases, rd.offsets, co, cb, max_edits=E)
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), (G, B, O, q)
+
+
+def test_verify_passing_candidates_uneven_recipe(oracle):
+    """The uneven-read candidate recipe (100/150/250 bp, e in 2..5 %, q = 6) on a 6 Mbp genome:
+    the filter's pass flags select the pairs to align; listed truth bins align within E."""
+    import torch
+    w = C.shrink(C.workload("c4"), genome_len=6_000_000, n_reads=3000)
+    w.genome.repeat_frac = 0.45
+    ref = synth.genome(w.genome)
+    rd = synth.reads(w.reads, ref)
+    co, cb = synth.candidates(ref, rd, w.bin_size, w.cand_cap, w.cand_k)
+    ep = rd.err_pm.astype(np.uint16)
+    idx = grim.grim_build_index(dev(ref), w.bin_size, w.overlap, w.q, grim.LAYOUT_BM | grim.LAYOUT_REF)
+    cnt = empty((len(cb),), torch.uint16)
+    pas = empty((len(cb),), torch.uint8)
+    rs = grim.ReadSet(dev(rd.bases), dev(rd.offsets), err_permille=dev(ep))
+    d_co, d_cb = dev(co), dev(cb)
+    grim.grim_filter_candidates(idx, rs, d_co, d_cb, cnt, pas)
+    dist = empty((len(cb),), torch.uint16)
+    match = empty((len(cb),), torch.uint8)
+    grim.grim_verify_candidates(idx, rs, d_co, d_cb, pas, dist, match)
+    torch.cuda.synchronize()
+    got_d = host(dist.view(torch.int16)).view(np.uint16)
+    got_m = host(match)
+    p = host(pas)
+    want_d, want_m = oracle.verify(ref, w.bin_size, w.overlap, w.q, rd.bases, rd.offsets, co, cb, verify_mask=p,
+                                   err_pm_per_read=ep)
+    assert np.array_equal(got_d, want_d) and np.array_equal(got_m, want_m)
+    rid = np.repeat(np.arange(rd.n), np.diff(co))
+    truth = cb == (rd.truth_pos // w.bin_size)[rid]
+    assert truth.sum() > rd.n // 2
+    assert got_m[truth].all()                 # every listed truth bin passed and maps
+    assert (got_d[truth] <= rd.n_edits[rid[truth]]).all()
+    log("uneven recipe: pairs", len(cb), "passing", int(p.sum()), "mapping", int(got_m.sum()),
+        "paper false-negative rate", 1.0 - float(got_m.sum()) / max(1, int(p.sum())))
+
+
+def test_verify_errors():
+    import torch
+    rng = random.Random(9)
+    ref = rand_ref(rng, 4000)
+    rd = synth.reads_from_strings([ref[100:180].tobytes()])
+    co, cb = np.array([0, 1], np.int64), np.array([0], np.int32)
+    dist, match = empty((1,), torch.uint16), empty((1,), torch.uint8)
+    rs = grim.ReadSet(dev(rd.bases), dev(rd.offsets), err_permille_all=50, allow_short_overlap=True)
+    no_ref = grim.grim_build_index(dev(ref), 1000, 100, 5, grim.LAYOUT_BM)
+    with pytest.raises(grim.GrimError) as e:
+        grim.grim_verify_candidates(no_ref, rs, dev(co), dev(cb), None, dist, match)
+    assert e.value.code == grim.GRIM_EINVAL
+    idx = grim.grim_build_index(dev(ref), 1000, 100, 5, grim.LAYOUT_REF)
+    with pytest.raises(grim.GrimError) as e:
+        grim.grim_verify_candidates(idx, rs, dev(co), dev(np.array([4], np.int32)), None, dist, match)
+    assert e.value.code == grim.GRIM_EINVAL
+    long = synth.reads_from_strings([ref[0:600].tobytes()])
+    rs_long = grim.ReadSet(dev(long.bases), dev(long.offsets), err_permille_all=50, allow_short_overlap=True)
+    with pytest.raises(grim.GrimError) as e:
+        grim.grim_verify_candidates(idx, rs_long, dev(co), dev(cb), None, dist, match)
+    assert e.value.code == grim.GRIM_EINVAL and "512" in str(e.value)
+    # the index is still usable
+    grim.grim_verify_candidates(idx, rs, dev(co), dev(cb), None, dist, match)
+    torch.cuda.synchronize()
+    assert int(host(dist.view(torch.int16))[0]) == 0 and int(host(match)[0]) == 1
