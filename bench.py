@@ -83,6 +83,8 @@ def parse():
                    help="directory where the synthetic seed-hit candidate lists are saved and reused "
                         "(saves minutes of host work when the same workload is run repeatedly)")
     p.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    p.add_argument("--no-verify", action="store_true",
+                   help="candidate workloads: skip aligning the passing pairs after the filter")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     p.add_argument("--calib-copy-mb", type=int, default=0,
                    help="run one plain device copy of this many MiB before timing (HBM counter calibration)")
@@ -139,7 +141,8 @@ def main():
         log(f"{len(cand[1]):,} seed-hit candidates in {time.time() - t0:.1f}s")
 
     stream = torch.cuda.current_stream()
-    layout = grim.LAYOUT_TM if w.mode == "allbins" else grim.LAYOUT_BM
+    # candidate workloads keep the reference in the index for the verification leg
+    layout = grim.LAYOUT_TM if w.mode == "allbins" else (grim.LAYOUT_BM | grim.LAYOUT_REF)
     dref = torch.from_numpy(ref).cuda()
     torch.cuda.synchronize()
     t0 = time.time()
@@ -264,6 +267,8 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, w, ref, rd, me, ep, idx, info, cand, mask if w.mode == "allbins"
                                            else (cnt, pas))
+    if w.mode == "candidates" and not args.no_verify:
+        out["verify"] = verify_leg(args, w, ref, rd, me, ep, reads, idx, cand, d_co, d_cb, pas, stream)
     if w.mode == "allbins" and args.serve_seconds > 0:
         del mask
         torch.cuda.synchronize()
@@ -277,6 +282,80 @@ def main():
                                    "plain_reads_per_s": sv["plain"]["reads_per_s"],
                                    "plain_p99_ms": sv["plain"]["p99_ms"]}
     print(json.dumps(out), flush=True)
+
+
+def verify_leg(args, w, ref, rd, me, ep, reads, idx, cand, d_co, d_cb, pas, stream):
+    """Align the pairs that passed the filter (the step after the filter) and report its time,
+    the filter's false-negative rate as the paper defines it (passing locations that yield no
+    mapping within E, over all passing locations), and a sampled check against the oracle."""
+    import torch
+    from paper_1708_04329_amd import grim
+    co, cb = cand
+    P = len(cb)
+    dist = torch.empty(max(P, 1), dtype=torch.uint16, device="cuda")
+    match = torch.empty(max(P, 1), dtype=torch.uint8, device="cuda")
+
+    def run():
+        grim.grim_verify_candidates(idx, reads, d_co, d_cb, pas, dist, match, stream)
+
+    run()
+    torch.cuda.synchronize()
+    grim.grim_profile_enable(True)
+    grim.grim_profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    elapsed = (time.perf_counter() - t0) / args.steps
+    prof = grim.grim_profile_read(reset=True)
+    grim.grim_profile_enable(False)
+    kt = prof["verify"]
+    align_ms = kt["total_ms"] / max(1, kt["launches"])
+    n_pass = int(pas[:P].sum(dtype=torch.int64).item())
+    n_map = int(match[:P].sum(dtype=torch.int64).item())
+    # DP cells: read length x bin bases, summed over the aligned pairs
+    lens = torch.from_numpy(rd.lengths).cuda()
+    rid = torch.repeat_interleave(torch.arange(rd.n, device="cuda", dtype=torch.int32), d_co[1:] - d_co[:-1])
+    sel = pas[:P].bool()
+    span = w.bin_size + w.overlap + w.q - 1
+    x = d_cb[sel].to(torch.int64)
+    G = len(ref)
+    last = min(G - w.q + 1, G)
+    hi = torch.clamp(x * w.bin_size + w.bin_size + w.overlap, max=last)
+    text = torch.where(hi > x * w.bin_size, hi + w.q - 1 - x * w.bin_size, torch.zeros_like(hi))
+    cells = int((lens[rid[sel]].to(torch.int64) * text).sum().item())
+    del rid, sel, x, hi, text
+    log(f"verify: {n_pass:,} passing pairs aligned in {align_ms:.2f} ms ({cells / (align_ms * 1e-3) / 1e9:.0f} "
+        f"GCUPS); {n_map:,} map; paper false-negative rate {1 - n_map / max(1, n_pass):.4f}")
+    res = {"pairs_aligned": n_pass, "mapping": n_map, "paper_false_negative_rate": 1 - n_map / max(1, n_pass),
+           "align_kernel_ms": align_ms, "call_ms": elapsed * 1e3, "dp_cells": cells,
+           "gcups": cells / (align_ms * 1e-3) / 1e9, "text_bases_per_bin": span}
+    if not args.no_cpu_baseline:
+        from oracle import Oracle
+        o = Oracle()
+        rng = np.random.default_rng(4321)
+        ids = np.sort(rng.choice(rd.n, size=min(rd.n, 400), replace=False))
+        sub = rd.subset(ids)
+        sco = np.zeros(len(ids) + 1, np.int64)
+        sco[1:] = np.cumsum(co[ids + 1] - co[ids])
+        pick = np.concatenate([np.arange(co[i], co[i + 1]) for i in ids])
+        tsel = torch.from_numpy(pick).cuda()
+        mask = pas[tsel].cpu().numpy()
+        t = time.perf_counter()
+        wd, wm = o.verify(ref, w.bin_size, w.overlap, w.q, sub.bases, sub.offsets, sco, cb[pick], verify_mask=mask,
+                          max_edits=None if me is None else me[ids], err_pm_per_read=None if ep is None else ep[ids])
+        dt = time.perf_counter() - t
+        gd = dist.view(torch.int16)[tsel].cpu().numpy().view(np.uint16)
+        gm = match[tsel].cpu().numpy()
+        sub_cells = int(sum(int(sub.lengths[np.searchsorted(sco, k, side="right") - 1]) for k in
+                            np.nonzero(mask)[0])) * span
+        res["cpu_oracle"] = {"gcups": sub_cells / dt / 1e9, "cores": o.threads_used(), "kind": "oracle",
+                             "sample": f"{len(ids)} reads (seeded), {int(mask.sum())} passing pairs aligned",
+                             "seconds": dt, "gpu_bit_exact_on_sample": bool(np.array_equal(gd, wd) and
+                                                                           np.array_equal(gm, wm))}
+        log(f"verify oracle: {int(mask.sum())} pairs in {dt:.1f}s; GPU bit-exact: "
+            f"{res['cpu_oracle']['gpu_bit_exact_on_sample']}")
+    return res
 
 
 def request_stream(seconds: float, rate: float, pool_n: int, seed: int, size_max: int = 20000):
