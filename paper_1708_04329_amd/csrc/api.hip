@@ -135,6 +135,7 @@ void free_workspace(grim_workspace& ws) {
   if (ws.vbucket_host) (void)hipHostFree(ws.vbucket_host);
   if (ws.vitem_pair) (void)hipFree(ws.vitem_pair);
   if (ws.vitem_read) (void)hipFree(ws.vitem_read);
+  if (ws.vread_sel) (void)hipFree(ws.vread_sel);
   ws = grim_workspace{};
 }
 
@@ -672,6 +673,8 @@ int grim_verify_candidates(const grim_index* cidx, const grim_reads* rd, const i
   if (!ws.vbucket_host)
     GRIM_HIP_TRY(hipHostMalloc(&ws.vbucket_host, 2 * kVerifyBuckets * sizeof(uint64_t), hipHostMallocDefault));
   GRIM_HIP_TRY(launch_zero_words(reinterpret_cast<uint32_t*>(ws.vbucket), 2 * kVerifyBuckets, s));
+  rc = grow(&ws.vread_sel, &ws.vread_sel_cap, rd->n_reads);
+  if (rc) return rc;
   VerifyArgs a{};
   a.ref = idx->ref;
   a.G = idx->G;
@@ -691,6 +694,7 @@ int grim_verify_candidates(const grim_index* cidx, const grim_reads* rd, const i
   a.match_out = match_out;
   a.status = ws.status;
   a.bucket = ws.vbucket;
+  a.read_sel = ws.vread_sel;
   GRIM_HIP_TRY(launch_verify_count(a, s));
   // pairs per length class, and the status of the inputs
   uint64_t* counts = ws.vbucket_host;

@@ -137,6 +137,7 @@ struct VerifyArgs {
   uint8_t* match_out;
   uint32_t* status;
   uint64_t* bucket;          // [kVerifyBuckets] counts, then cursors
+  uint32_t* read_sel;        // [n_reads] pairs selected per read (first pass)
   uint64_t* item_pair;       // work list: pair index
   uint32_t* item_read;       //            and its read
 };
@@ -268,6 +269,8 @@ struct grim_workspace {
   uint64_t* vitem_pair = nullptr;    // verification work list
   uint32_t* vitem_read = nullptr;
   uint64_t vitem_cap = 0, vitem_read_cap = 0;
+  uint32_t* vread_sel = nullptr;     // pairs selected per read
+  uint64_t vread_sel_cap = 0;
 };
 
 struct grim_index {

@@ -15,6 +15,11 @@
 // alignment may start anywhere in the text, and the distance is the minimum
 // over all columns of the last row.
 //
+// The read's match masks are kept as two code bit planes and a validity
+// plane, so a text base selects its mask with two three-input operations
+// per word; 16-byte text chunks holding a byte other than A, C, G, T (N
+// runs) take a checked step that masks it out.
+//
 // Work split: one lane per pair. A first pass counts the pairs to align per
 // read length class (words per read, 1..16) and writes the outputs of the
 // pairs it skips; a second pass lists the pairs class by class, so that one
@@ -27,6 +32,13 @@ namespace {
 
 constexpr uint32_t kSkipped = 0xFFFFu;
 
+// Selection of pair k: a valid bin, and the mask (if any) set. Loads are
+// issued for 4 consecutive 64-pair groups at once so that a wavefront has
+// several memory round trips in flight.
+__device__ __forceinline__ bool selected(const VerifyArgs& a, int32_t x, uint8_t m) {
+  return x >= 0 && (uint64_t)x < a.nb && (!a.verify_mask || m);
+}
+
 __global__ __launch_bounds__(256) void k_verify_count(VerifyArgs a) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t r = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -38,22 +50,34 @@ __global__ __launch_bounds__(256) void k_verify_count(VerifyArgs a) {
     return;
   }
   const uint64_t L = (uint64_t)(a.offsets[r + 1] - a.offsets[r]);
-  uint64_t n_sel = 0;
-  for (int64_t k0 = c0; k0 < c1; k0 += 64) {
-    const int64_t k = k0 + lane;
-    bool sel = false;
-    if (k < c1) {
-      const int32_t x = a.cand_bin[k];
-      if (x < 0 || (uint64_t)x >= a.nb) atomicOr(a.status, ST_BAD_BIN);
-      else sel = !a.verify_mask || a.verify_mask[k];
-      if (!sel) {
-        a.dist_out[k] = (uint16_t)kSkipped;
-        a.match_out[k] = 0;
-      }
+  uint32_t n_sel = 0;
+  for (int64_t k0 = c0; k0 < c1; k0 += 4 * 64) {
+    int32_t x[4];
+    uint8_t m[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = k0 + u * 64 + lane;
+      x[u] = k < c1 ? a.cand_bin[k] : 0;
+      m[u] = (k < c1 && a.verify_mask) ? a.verify_mask[k] : 1;
     }
-    n_sel += (uint64_t)__popcll(__ballot(sel));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = k0 + u * 64 + lane;
+      bool sel = false;
+      if (k < c1) {
+        if (x[u] < 0 || (uint64_t)x[u] >= a.nb) atomicOr(a.status, ST_BAD_BIN);
+        sel = selected(a, x[u], m[u]);
+        if (!sel) {
+          a.dist_out[k] = (uint16_t)kSkipped;
+          a.match_out[k] = 0;
+        }
+      }
+      n_sel += (uint32_t)__popcll(__ballot(sel));
+    }
   }
-  if (n_sel == 0 || lane != 0) return;
+  if (lane != 0) return;
+  a.read_sel[r] = n_sel;
+  if (n_sel == 0) return;
   if (L > kVerifyMaxLen || L == 0) {
     atomicOr(a.status, ST_VERIFY_LONG);
     return;
@@ -61,67 +85,86 @@ __global__ __launch_bounds__(256) void k_verify_count(VerifyArgs a) {
   atomicAdd(reinterpret_cast<unsigned long long*>(a.bucket + (L + 31) / 32), (unsigned long long)n_sel);
 }
 
+// One cursor reservation per read (its count from the first pass), then the
+// read's selected pairs take consecutive slots in pair order.
 __global__ __launch_bounds__(256) void k_verify_scatter(VerifyArgs a) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t r = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= a.n_reads) return;
+  const uint32_t n_sel = a.read_sel[r];
+  if (n_sel == 0) return;
   const int64_t c0 = a.cand_off[r], c1 = a.cand_off[r + 1];
   const uint64_t L = (uint64_t)(a.offsets[r + 1] - a.offsets[r]);
-  if (L == 0 || L > kVerifyMaxLen) return;
   unsigned long long* cursor = reinterpret_cast<unsigned long long*>(a.bucket + (L + 31) / 32);
-  for (int64_t k0 = c0; k0 < c1; k0 += 64) {
-    const int64_t k = k0 + lane;
-    bool sel = false;
-    if (k < c1) {
-      const int32_t x = a.cand_bin[k];
-      sel = x >= 0 && (uint64_t)x < a.nb && (!a.verify_mask || a.verify_mask[k]);
+  uint64_t base = 0;
+  if (lane == 0) base = atomicAdd(cursor, (unsigned long long)n_sel);
+  base = ((uint64_t)(uint32_t)__shfl((int)(base >> 32), 0) << 32) | (uint32_t)__shfl((int)(uint32_t)base, 0);
+  for (int64_t k0 = c0; k0 < c1; k0 += 4 * 64) {
+    int32_t x[4];
+    uint8_t m[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = k0 + u * 64 + lane;
+      x[u] = k < c1 ? a.cand_bin[k] : -1;
+      m[u] = (k < c1 && a.verify_mask) ? a.verify_mask[k] : 1;
     }
-    const uint64_t m = __ballot(sel);
-    if (m == 0) continue;
-    uint64_t base = 0;
-    if (lane == 0) base = atomicAdd(cursor, (unsigned long long)__popcll(m));
-    base = ((uint64_t)(uint32_t)__shfl((int)(base >> 32), 0) << 32) | (uint32_t)__shfl((int)(uint32_t)base, 0);
-    if (sel) {
-      const uint64_t below = m & ((1ull << lane) - 1ull);
-      const uint64_t pos = base + (uint64_t)__popcll(below);
-      a.item_pair[pos] = (uint64_t)k;
-      a.item_read[pos] = (uint32_t)r;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = k0 + u * 64 + lane;
+      const bool sel = k < c1 && selected(a, x[u], m[u]);
+      const uint64_t bal = __ballot(sel);
+      if (sel) {
+        const uint64_t pos = base + (uint64_t)__popcll(bal & ((1ull << lane) - 1ull));
+        a.item_pair[pos] = (uint64_t)k;
+        a.item_read[pos] = (uint32_t)r;
+      }
+      base += (uint64_t)__popcll(bal);
     }
   }
 }
 
-// Myers' column step for W words. pe[c][w]: bit i of word w set when read
-// base 32w + i has code c. pv/mv: vertical +1/-1 bits of the current column.
-// `top` is the read's last row within word W - 1; `score` tracks that row.
+// Myers' column step for W words. The read is held as bit planes: bit i of
+// word w of r0 / r1 is bit 0 / bit 1 of the code of read base 32w + i, and
+// va marks the bases that are A, C, G or T; so the match mask of text code c
+// is va & ~(r0 ^ c0) & ~(r1 ^ c1) with c0, c1 the bits of c spread to all
+// 32 positions, two three-input operations per word. pv/mv: vertical +1/-1
+// bits of the current column; `top` is the read's last row within word
+// W - 1, whose distance `score` tracks. CHECKED steps also accept text bytes
+// other than 0..3 (they match nothing).
 template <int W>
 struct Column {
-  uint32_t pe[4][W];
+  uint32_t r0[W], r1[W], va[W];
   uint32_t pv[W], mv[W];
   uint32_t top;
   int32_t score, best;
 
+  template <bool CHECKED>
   __device__ __forceinline__ void step(uint32_t c) {
-    const uint32_t valid = c < 4u ? 0xFFFFFFFFu : 0u;  // other bytes match nothing
-    const bool odd = (c & 1u) != 0, high = (c & 2u) != 0;
-    uint32_t hp = 0, hm = 0;  // horizontal difference entering word w's bottom row
+    const uint32_t c0 = 0u - (c & 1u), c1 = 0u - ((c >> 1) & 1u);
+    const uint32_t valid = (!CHECKED || c < 4u) ? 0xFFFFFFFFu : 0u;
+    // the previous word's unshifted horizontal +1/-1 bits: their top bit is
+    // the difference entering this word's bottom row (0 below word 0)
+    uint32_t php = 0, mhp = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-      const uint32_t ac = odd ? pe[1][w] : pe[0][w];
-      const uint32_t gt = odd ? pe[3][w] : pe[2][w];
-      uint32_t eq = (high ? gt : ac) & valid;
+      // truth tables of bitop3 over (src0, src1, src2) = 0xF0, 0xCC, 0xAA
+      uint32_t eq = __builtin_amdgcn_bitop3_b32(va[w], r0[w], c0, 0x90);  // va & ~(r0 ^ c0)
+      eq = __builtin_amdgcn_bitop3_b32(eq, r1[w], c1, 0x90);              //    & ~(r1 ^ c1)
+      if (CHECKED) eq &= valid;
       const uint32_t xv = eq | mv[w];
-      eq |= hm;  // a -1 entering from below acts as a match in the carry chain
-      const uint32_t xh = (((eq & pv[w]) + pv[w]) ^ pv[w]) | eq;
-      uint32_t ph = mv[w] | ~(xh | pv[w]);
-      uint32_t mh = pv[w] & xh;
+      eq |= mhp >> 31;  // a -1 entering from below acts as a match in the carry chain
+      const uint32_t sum = (eq & pv[w]) + pv[w];
+      const uint32_t xh = __builtin_amdgcn_bitop3_b32(sum, pv[w], eq, 0xBE);  // (sum ^ pv) | eq
+      const uint32_t ph = mv[w] | ~(xh | pv[w]);
+      const uint32_t mh = pv[w] & xh;
       if (w == W - 1) score += (int32_t)((ph >> top) & 1u) - (int32_t)((mh >> top) & 1u);
-      const uint32_t hp_out = ph >> 31, hm_out = mh >> 31;
-      ph = (ph << 1) | hp;
-      mh = (mh << 1) | hm;
-      pv[w] = mh | ~(xv | ph);
-      mv[w] = ph & xv;
-      hp = hp_out;
-      hm = hm_out;
+      // shift up one row, the entering difference moving into row 0
+      const uint32_t phs = __builtin_amdgcn_alignbit(ph, php, 31);
+      const uint32_t mhs = __builtin_amdgcn_alignbit(mh, mhp, 31);
+      pv[w] = mhs | ~(xv | phs);
+      mv[w] = phs & xv;
+      php = ph;
+      mhp = mh;
     }
     best = min(best, score);
   }
@@ -148,21 +191,20 @@ __global__ __launch_bounds__(256) void k_verify_align(VerifyArgs a, uint64_t fir
   const uint8_t* rd = a.bases + o0;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+    uint32_t b0 = 0, b1 = 0, ok = 0;
     for (uint32_t b = 0; b < 32; ++b) {
       const uint32_t i = (uint32_t)w * 32 + b;
       if (i >= L) break;
-      const uint32_t c = rd[i] | 0x20u;  // fold ASCII letters to lower case
+      const uint32_t ch = rd[i] | 0x20u;  // fold ASCII letters to lower case
+      const uint32_t code = ch == 'a' ? 0u : ch == 'c' ? 1u : ch == 'g' ? 2u : ch == 't' ? 3u : 4u;
       const uint32_t bit = 1u << b;
-      m0 |= c == 'a' ? bit : 0u;
-      m1 |= c == 'c' ? bit : 0u;
-      m2 |= c == 'g' ? bit : 0u;
-      m3 |= c == 't' ? bit : 0u;
+      b0 |= (code & 1u) ? bit : 0u;
+      b1 |= (code & 2u) ? bit : 0u;
+      ok |= code < 4u ? bit : 0u;
     }
-    col.pe[0][w] = m0;
-    col.pe[1][w] = m1;
-    col.pe[2][w] = m2;
-    col.pe[3][w] = m3;
+    col.r0[w] = b0;
+    col.r1[w] = b1;
+    col.va[w] = ok;
     col.pv[w] = 0xFFFFFFFFu;  // column 0: row i holds distance i
     col.mv[w] = 0;
   }
@@ -173,16 +215,23 @@ __global__ __launch_bounds__(256) void k_verify_align(VerifyArgs a, uint64_t fir
   const uint8_t* txt = a.ref;
   uint64_t j = lo;
   const uint64_t aligned = min(hi, (lo + 15) & ~15ull);
-  for (; j < aligned; ++j) col.step(txt[j]);
+  for (; j < aligned; ++j) col.template step<true>(txt[j]);
   for (; j + 16 <= hi; j += 16) {
     const uint4 v = *reinterpret_cast<const uint4*>(txt + j);
     const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+    if (((v.x | v.y | v.z | v.w) & 0xFCFCFCFCu) == 0) {  // A, C, G, T only (the common case)
 #pragma unroll
-    for (int q4 = 0; q4 < 4; ++q4)
+      for (int q4 = 0; q4 < 4; ++q4)
 #pragma unroll
-      for (int by = 0; by < 4; ++by) col.step((wv[q4] >> (8 * by)) & 0xFFu);
+        for (int by = 0; by < 4; ++by) col.template step<false>((wv[q4] >> (8 * by)) & 0xFFu);
+    } else {
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4)
+#pragma unroll
+        for (int by = 0; by < 4; ++by) col.template step<true>((wv[q4] >> (8 * by)) & 0xFFu);
+    }
   }
-  for (; j < hi; ++j) col.step(txt[j]);
+  for (; j < hi; ++j) col.template step<true>(txt[j]);
 
   const int32_t T = a.thr[r];
   const int64_t E = ((int64_t)L - (int64_t)a.q + 1 - (int64_t)T) / (int64_t)a.q;
