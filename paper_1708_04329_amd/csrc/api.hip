@@ -136,6 +136,7 @@ void free_workspace(grim_workspace& ws) {
   if (ws.vitem_pair) (void)hipFree(ws.vitem_pair);
   if (ws.vitem_read) (void)hipFree(ws.vitem_read);
   if (ws.vread_sel) (void)hipFree(ws.vread_sel);
+  if (ws.vchunk_sum) (void)hipFree(ws.vchunk_sum);
   ws = grim_workspace{};
 }
 
@@ -672,8 +673,9 @@ int grim_verify_candidates(const grim_index* cidx, const grim_reads* rd, const i
   if (!ws.vbucket) GRIM_HIP_TRY(hipMalloc(&ws.vbucket, kVerifyBuckets * sizeof(uint64_t)));
   if (!ws.vbucket_host)
     GRIM_HIP_TRY(hipHostMalloc(&ws.vbucket_host, 2 * kVerifyBuckets * sizeof(uint64_t), hipHostMallocDefault));
-  GRIM_HIP_TRY(launch_zero_words(reinterpret_cast<uint32_t*>(ws.vbucket), 2 * kVerifyBuckets, s));
   rc = grow(&ws.vread_sel, &ws.vread_sel_cap, rd->n_reads);
+  if (rc) return rc;
+  rc = grow(&ws.vchunk_sum, &ws.vchunk_sum_cap, verify_chunks(rd->n_reads) * kVerifyBuckets);
   if (rc) return rc;
   VerifyArgs a{};
   a.ref = idx->ref;
@@ -695,6 +697,7 @@ int grim_verify_candidates(const grim_index* cidx, const grim_reads* rd, const i
   a.status = ws.status;
   a.bucket = ws.vbucket;
   a.read_sel = ws.vread_sel;
+  a.chunk_sum = ws.vchunk_sum;
   GRIM_HIP_TRY(launch_verify_count(a, s));
   // pairs per length class, and the status of the inputs
   uint64_t* counts = ws.vbucket_host;
@@ -715,7 +718,6 @@ int grim_verify_candidates(const grim_index* cidx, const grim_reads* rd, const i
   if (rc) return rc;
   a.item_pair = ws.vitem_pair;
   a.item_read = ws.vitem_read;
-  GRIM_HIP_TRY(hipMemcpyAsync(ws.vbucket, first, kVerifyBuckets * sizeof(uint64_t), hipMemcpyHostToDevice, s));
   GRIM_HIP_TRY(launch_verify_scatter(a, s));
   ProfSpan pv(PROF_VERIFY);
   pv.start(s);

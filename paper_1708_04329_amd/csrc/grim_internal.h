@@ -120,6 +120,7 @@ hipError_t launch_ref_codes(const uint8_t* ref, uint64_t G, uint8_t* codes, hipS
 // of the read against the bases of the bin's extent.
 constexpr uint32_t kVerifyMaxLen = 512;   // bases per read: 16 words of 32 rows
 constexpr uint32_t kVerifyBuckets = 17;   // work lists by words per read, 1..16
+constexpr uint32_t kVerifyChunk = 2048;   // reads per workgroup of the list passes
 struct VerifyArgs {
   const uint8_t* ref;        // base codes, G bytes
   uint64_t G;
@@ -136,14 +137,18 @@ struct VerifyArgs {
   uint16_t* dist_out;
   uint8_t* match_out;
   uint32_t* status;
-  uint64_t* bucket;          // [kVerifyBuckets] counts, then cursors
+  uint64_t* bucket;          // [kVerifyBuckets] pairs to align per class
   uint32_t* read_sel;        // [n_reads] pairs selected per read (first pass)
+  uint64_t* chunk_sum;       // [chunks][kVerifyBuckets] pair counts, then first slots
   uint64_t* item_pair;       // work list: pair index
   uint32_t* item_read;       //            and its read
 };
-// Count the pairs to align per bucket (and write the outputs of skipped pairs).
+// Chunks of reads of the list passes.
+uint64_t verify_chunks(uint64_t n_reads);
+// Count the pairs to align per class into a.bucket and per chunk (and write
+// the outputs of skipped pairs); list positions follow classes in order.
 hipError_t launch_verify_count(const VerifyArgs& a, hipStream_t s);
-// Fill the work lists; a.bucket holds each bucket's first slot on entry.
+// Fill the work list from the counts and positions of launch_verify_count.
 hipError_t launch_verify_scatter(const VerifyArgs& a, hipStream_t s);
 // Align work items [first, first + count), all of whose reads have `words`
 // 32-base words.
@@ -271,6 +276,8 @@ struct grim_workspace {
   uint64_t vitem_cap = 0, vitem_read_cap = 0;
   uint32_t* vread_sel = nullptr;     // pairs selected per read
   uint64_t vread_sel_cap = 0;
+  uint64_t* vchunk_sum = nullptr;    // per-chunk class counts / first slots
+  uint64_t vchunk_sum_cap = 0;
 };
 
 struct grim_index {

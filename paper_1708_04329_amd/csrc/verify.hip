@@ -22,7 +22,9 @@
 //
 // Work split: one lane per pair. A first pass counts the pairs to align per
 // read length class (words per read, 1..16) and writes the outputs of the
-// pairs it skips; a second pass lists the pairs class by class, so that one
+// pairs it skips; a prefix over chunks of reads turns the counts into list
+// positions (no global atomics, which would serialise on a few class
+// counters); a second pass lists the pairs class by class, so that one
 // launch per class runs lanes with equal word counts in lock step.
 
 #include "grim_internal.h"
@@ -31,94 +33,173 @@ namespace grim {
 namespace {
 
 constexpr uint32_t kSkipped = 0xFFFFu;
+constexpr int kGroups = 16;
 
-// Selection of pair k: a valid bin, and the mask (if any) set. Loads are
-// issued for 4 consecutive 64-pair groups at once so that a wavefront has
-// several memory round trips in flight.
+// Selection of pair k: a valid bin, and the mask (if any) set.
 __device__ __forceinline__ bool selected(const VerifyArgs& a, int32_t x, uint8_t m) {
   return x >= 0 && (uint64_t)x < a.nb && (!a.verify_mask || m);
 }
 
-__global__ __launch_bounds__(256) void k_verify_count(VerifyArgs a) {
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint64_t r = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= a.n_reads) return;
-  if (a.status[0] & ~(uint32_t)(ST_BAD_BIN | ST_BAD_CAND_OFF | ST_VERIFY_LONG)) return;  // rejected reads
-  const int64_t c0 = a.cand_off[r], c1 = a.cand_off[r + 1];
-  if (c0 < 0 || c1 < c0 || (uint64_t)c1 > a.n_cand) {
-    if (lane == 0) atomicOr(a.status, ST_BAD_CAND_OFF);
-    return;
-  }
-  const uint64_t L = (uint64_t)(a.offsets[r + 1] - a.offsets[r]);
-  uint32_t n_sel = 0;
-  for (int64_t k0 = c0; k0 < c1; k0 += 4 * 64) {
-    int32_t x[4];
-    uint8_t m[4];
+// Bin ids and mask bytes of kGroups consecutive 64-pair groups from k0, all
+// loads issued before the first wait (past the end: the read's last pair,
+// ignored by the caller).
+__device__ __forceinline__ void load_groups(const VerifyArgs& a, int64_t k0, int64_t c1, uint32_t lane,
+                                            int32_t (&x)[kGroups], uint8_t (&m)[kGroups]) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t k = k0 + u * 64 + lane;
-      x[u] = k < c1 ? a.cand_bin[k] : 0;
-      m[u] = (k < c1 && a.verify_mask) ? a.verify_mask[k] : 1;
-    }
+  for (int u = 0; u < kGroups; ++u) x[u] = a.cand_bin[min(k0 + u * 64 + (int64_t)lane, c1 - 1)];
+  if (a.verify_mask) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t k = k0 + u * 64 + lane;
-      bool sel = false;
-      if (k < c1) {
-        if (x[u] < 0 || (uint64_t)x[u] >= a.nb) atomicOr(a.status, ST_BAD_BIN);
-        sel = selected(a, x[u], m[u]);
-        if (!sel) {
-          a.dist_out[k] = (uint16_t)kSkipped;
-          a.match_out[k] = 0;
-        }
-      }
-      n_sel += (uint32_t)__popcll(__ballot(sel));
-    }
+    for (int u = 0; u < kGroups; ++u) m[u] = a.verify_mask[min(k0 + u * 64 + (int64_t)lane, c1 - 1)];
+  } else {
+#pragma unroll
+    for (int u = 0; u < kGroups; ++u) m[u] = 1;
   }
-  if (lane != 0) return;
-  a.read_sel[r] = n_sel;
-  if (n_sel == 0) return;
-  if (L > kVerifyMaxLen || L == 0) {
-    atomicOr(a.status, ST_VERIFY_LONG);
-    return;
-  }
-  atomicAdd(reinterpret_cast<unsigned long long*>(a.bucket + (L + 31) / 32), (unsigned long long)n_sel);
 }
 
-// One cursor reservation per read (its count from the first pass), then the
-// read's selected pairs take consecutive slots in pair order.
-__global__ __launch_bounds__(256) void k_verify_scatter(VerifyArgs a) {
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint64_t r = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= a.n_reads) return;
-  const uint32_t n_sel = a.read_sel[r];
-  if (n_sel == 0) return;
-  const int64_t c0 = a.cand_off[r], c1 = a.cand_off[r + 1];
+__device__ __forceinline__ uint32_t length_class(const VerifyArgs& a, uint64_t r) {
   const uint64_t L = (uint64_t)(a.offsets[r + 1] - a.offsets[r]);
-  unsigned long long* cursor = reinterpret_cast<unsigned long long*>(a.bucket + (L + 31) / 32);
-  uint64_t base = 0;
-  if (lane == 0) base = atomicAdd(cursor, (unsigned long long)n_sel);
-  base = ((uint64_t)(uint32_t)__shfl((int)(base >> 32), 0) << 32) | (uint32_t)__shfl((int)(uint32_t)base, 0);
-  for (int64_t k0 = c0; k0 < c1; k0 += 4 * 64) {
-    int32_t x[4];
-    uint8_t m[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t k = k0 + u * 64 + lane;
-      x[u] = k < c1 ? a.cand_bin[k] : -1;
-      m[u] = (k < c1 && a.verify_mask) ? a.verify_mask[k] : 1;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t k = k0 + u * 64 + lane;
-      const bool sel = k < c1 && selected(a, x[u], m[u]);
-      const uint64_t bal = __ballot(sel);
-      if (sel) {
-        const uint64_t pos = base + (uint64_t)__popcll(bal & ((1ull << lane) - 1ull));
-        a.item_pair[pos] = (uint64_t)k;
-        a.item_read[pos] = (uint32_t)r;
+  return (L == 0 || L > kVerifyMaxLen) ? 0u : (uint32_t)((L + 31) / 32);
+}
+
+// First pass, one workgroup of 16 wavefronts per chunk of kVerifyChunk reads,
+// a wavefront per read: count the read's selected pairs (read_sel), write the outputs of the
+// pairs it skips, and sum the counts per length class for the chunk
+// (chunk_sum[chunk][class]). No global atomics: the list positions come from
+// a prefix over chunks.
+__global__ __launch_bounds__(1024) void k_verify_count(VerifyArgs a) {
+  __shared__ unsigned long long csum[kVerifyBuckets];
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  if (threadIdx.x < kVerifyBuckets) csum[threadIdx.x] = 0;
+  __syncthreads();
+  const bool rejected = a.status[0] & ~(uint32_t)(ST_BAD_BIN | ST_BAD_CAND_OFF | ST_VERIFY_LONG);
+  const uint64_t r_lo = (uint64_t)blockIdx.x * kVerifyChunk;
+  const uint64_t r_hi = min(a.n_reads, r_lo + kVerifyChunk);
+  for (uint64_t r = r_lo + wave; r < r_hi && !rejected; r += 16) {
+    const int64_t c0 = a.cand_off[r], c1 = a.cand_off[r + 1];
+    if (c0 < 0 || c1 < c0 || (uint64_t)c1 > a.n_cand || c1 - c0 > 0xFFFFFFFFll) {
+      if (lane == 0) {
+        atomicOr(a.status, ST_BAD_CAND_OFF);
+        a.read_sel[r] = 0;
       }
-      base += (uint64_t)__popcll(bal);
+      continue;
+    }
+    uint32_t n_sel = 0;
+    for (int64_t k0 = c0; k0 < c1; k0 += kGroups * 64) {
+      int32_t x[kGroups];
+      uint8_t m[kGroups];
+      load_groups(a, k0, c1, lane, x, m);
+#pragma unroll
+      for (int u = 0; u < kGroups; ++u) {
+        const int64_t k = k0 + u * 64 + lane;
+        bool sel = false;
+        if (k < c1) {
+          if (x[u] < 0 || (uint64_t)x[u] >= a.nb) atomicOr(a.status, ST_BAD_BIN);
+          sel = selected(a, x[u], m[u]);
+          if (!sel) {
+            a.dist_out[k] = (uint16_t)kSkipped;
+            a.match_out[k] = 0;
+          }
+        }
+        n_sel += (uint32_t)__popcll(__ballot(sel));
+      }
+    }
+    if (lane == 0) {
+      a.read_sel[r] = n_sel;
+      if (n_sel) {
+        const uint32_t cls = length_class(a, r);
+        if (cls == 0) atomicOr(a.status, ST_VERIFY_LONG);
+        else atomicAdd(&csum[cls], (unsigned long long)n_sel);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kVerifyBuckets) a.chunk_sum[(uint64_t)blockIdx.x * kVerifyBuckets + threadIdx.x] = csum[threadIdx.x];
+}
+
+// One wavefront per length class 1..16 (class 0 holds no pairs): a scan
+// over the chunks, 64 at a time, turns chunk_sum[chunk][class] into the list
+// slot of the chunk's first pair of that class; bucket[class] gets the
+// class's pair count (the host launches one alignment per class). Classes
+// follow each other in the list in increasing order.
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, uint32_t d) {
+  const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, d), hi = (uint32_t)__shfl_up((int)(v >> 32), d);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__global__ __launch_bounds__(1024) void k_verify_prefix(VerifyArgs a, uint64_t n_chunks) {
+  __shared__ unsigned long long total[kVerifyBuckets];
+  const uint32_t lane = threadIdx.x & 63u, c = 1 + (threadIdx.x >> 6);  // classes 1..16
+  unsigned long long acc = 0;
+  for (uint64_t k0 = 0; k0 < n_chunks; k0 += 64) {
+    const uint64_t k = k0 + lane;
+    const uint64_t v = k < n_chunks ? a.chunk_sum[k * kVerifyBuckets + c] : 0;
+    uint64_t incl = v;
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+      const uint64_t t = shfl_up64(incl, d);
+      if (lane >= d) incl += t;
+    }
+    if (k < n_chunks) a.chunk_sum[k * kVerifyBuckets + c] = acc + incl - v;
+    const uint64_t sum64 = ((uint64_t)(uint32_t)__shfl((int)(incl >> 32), 63) << 32) |
+                           (uint32_t)__shfl((int)(uint32_t)incl, 63);
+    acc += sum64;
+  }
+  if (lane == 0) total[c] = acc;
+  if (threadIdx.x == 0) total[0] = 0;
+  __syncthreads();
+  unsigned long long first = 0;
+  for (uint32_t i = 0; i < c; ++i) first += total[i];
+  for (uint64_t k = lane; k < n_chunks; k += 64) a.chunk_sum[k * kVerifyBuckets + c] += first;
+  if (lane == 0) a.bucket[c] = acc;
+  if (threadIdx.x == 0) a.bucket[0] = 0;
+}
+
+// Second pass, same chunks: the reads' first slots, in read order within each
+// class (one thread per class over the chunk), then each wavefront lists its
+// read's selected pairs in pair order.
+__global__ __launch_bounds__(1024) void k_verify_scatter(VerifyArgs a) {
+  __shared__ unsigned long long base[kVerifyChunk];
+  __shared__ uint32_t sel_s[kVerifyChunk];
+  __shared__ uint8_t cls_s[kVerifyChunk];
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint64_t r_lo = (uint64_t)blockIdx.x * kVerifyChunk;
+  const uint64_t r_hi = min(a.n_reads, r_lo + kVerifyChunk);
+  const uint32_t n = (uint32_t)(r_hi - r_lo);
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    sel_s[i] = a.read_sel[r_lo + i];
+    cls_s[i] = (uint8_t)length_class(a, r_lo + i);
+  }
+  __syncthreads();
+  if (threadIdx.x < kVerifyBuckets) {
+    unsigned long long cur = a.chunk_sum[(uint64_t)blockIdx.x * kVerifyBuckets + threadIdx.x];
+    for (uint32_t i = 0; i < n; ++i) {
+      if (cls_s[i] != threadIdx.x) continue;
+      base[i] = cur;
+      cur += sel_s[i];
+    }
+  }
+  __syncthreads();
+  for (uint64_t r = r_lo + wave; r < r_hi; r += 16) {
+    const uint32_t i = (uint32_t)(r - r_lo);
+    if (sel_s[i] == 0 || cls_s[i] == 0) continue;
+    const int64_t c0 = a.cand_off[r], c1 = a.cand_off[r + 1];
+    uint64_t pos0 = base[i];
+    for (int64_t k0 = c0; k0 < c1; k0 += kGroups * 64) {
+      int32_t x[kGroups];
+      uint8_t m[kGroups];
+      load_groups(a, k0, c1, lane, x, m);
+#pragma unroll
+      for (int u = 0; u < kGroups; ++u) {
+        const int64_t k = k0 + u * 64 + lane;
+        const bool sel = k < c1 && selected(a, x[u], m[u]);
+        const uint64_t bal = __ballot(sel);
+        if (sel) {
+          const uint64_t pos = pos0 + (uint64_t)__popcll(bal & ((1ull << lane) - 1ull));
+          a.item_pair[pos] = (uint64_t)k;
+          a.item_read[pos] = (uint32_t)r;
+        }
+        pos0 += (uint64_t)__popcll(bal);
+      }
     }
   }
 }
@@ -250,19 +331,23 @@ hipError_t launch_align_w(const VerifyArgs& a, uint64_t first, uint64_t count, h
 
 }  // namespace
 
+uint64_t verify_chunks(uint64_t n_reads) { return (n_reads + kVerifyChunk - 1) / kVerifyChunk; }
+
 hipError_t launch_verify_count(const VerifyArgs& a, hipStream_t s) {
-  const uint64_t blocks = (a.n_reads + 3) / 4;
-  if (blocks == 0) return hipSuccess;
-  if (blocks > 0x7FFFFFFFull) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(k_verify_count, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  const uint64_t chunks = verify_chunks(a.n_reads);
+  if (chunks == 0) return hipSuccess;
+  if (chunks > 0x7FFFFFFFull) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_verify_count, dim3((unsigned)chunks), dim3(1024), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_verify_prefix, dim3(1), dim3(1024), 0, s, a, chunks);
   return hipGetLastError();
 }
 
 hipError_t launch_verify_scatter(const VerifyArgs& a, hipStream_t s) {
-  const uint64_t blocks = (a.n_reads + 3) / 4;
-  if (blocks == 0) return hipSuccess;
-  if (blocks > 0x7FFFFFFFull) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(k_verify_scatter, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  const uint64_t chunks = verify_chunks(a.n_reads);
+  if (chunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_verify_scatter, dim3((unsigned)chunks), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 
