@@ -24,9 +24,11 @@
 // tokens then stay in that XCD's L2.
 //
 // Full 32-token blocks go through the Harley-Seal tree, two blocks per step
-// so that only every other block's carry ripples through the upper planes;
-// the remainder of a read is folded exactly as power-of-two parts, so no padding token costs
-// work unless another read of the wavefront needs that part. Counters have
+// so that only every other block's carry ripples through the upper planes.
+// The remainder of a read is folded first, exactly, as power-of-two parts in
+// increasing size: each part's carry lands in a still-empty plane and needs
+// no ripple, and no padding token costs work unless another read of the
+// wavefront needs that part. Counters have
 // 8 planes (counts up to 255); a wavefront holding a longer read switches to
 // 16 planes and covers its words in 2-word passes, which keeps that path
 // within the registers of the common one.
@@ -160,20 +162,23 @@ __device__ __forceinline__ void load_part(uint32_t (&tk)[N], const uint32_t* src
   }
 }
 
-// Fold N = 2^k tokens into the counters: a tree into planes 0..k-1 whose
-// carry of weight N enters at plane k.
+// Fold N = 2^k tokens of a read's remainder into the counters. Parts are
+// folded first, in increasing size, so before part 2^k the count is at most
+// 1 + 2 + ... + 2^(k-1) < 2^k: plane k and every plane above it are still
+// zero, and the tree's carry of weight 2^k simply becomes plane k (no ripple).
 template <int N, int LW, int NHI>
 __device__ __forceinline__ void fold_part(Counters<LW, NHI>& c, const char* lds_lane, const uint32_t (&tk)[N]) {
   constexpr int L = (N == 1) ? 0 : (N == 2) ? 1 : (N == 4) ? 2 : (N == 8) ? 3 : 4;
-  uint32_t carry[LW];
   if constexpr (N == 1) {
     const Words<LW> x = lds_row<LW>(reinterpret_cast<const uint32_t*>(lds_lane + tk[0]));
 #pragma unroll
-    for (int j = 0; j < LW; ++j) carry[j] = x.w[j];
+    for (int j = 0; j < LW; ++j) c.p[0][j] = x.w[j];
   } else {
+    uint32_t carry[LW];
     tree<N, LW, NHI>(c, lds_lane, tk, carry);
+#pragma unroll
+    for (int j = 0; j < LW; ++j) c.p[L][j] = carry[j];
   }
-  add_carry<L, LW, NHI>(c, carry);
 }
 
 // Threshold test on 32 bit-sliced counters of NP planes: bit b of the result
@@ -200,6 +205,28 @@ __device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lan
 #pragma unroll
     for (int j = 0; j < LW; ++j) c.p[k][j] = 0;
   const uint32_t nfull = active ? ntok >> 5 : 0;
+  // The last partial block first, folded exactly as 1/2/4/8/16-token parts
+  // into the empty counters: part 2^k is folded when any lane's remainder
+  // has bit k, so the parts cover every lane's remainder, and a lane reads
+  // zero-row padding past its own (every token list ends with at least one
+  // padding token and is padded to a multiple of 32). The parts' token loads
+  // are all issued before the first fold so that their latencies overlap.
+  const uint32_t rem = active ? (ntok & 31u) : 0u;
+  const uint32_t* tail = active ? tok + (uint64_t)nfull * 32 : nullptr;
+  const bool h16 = __any(rem & 16u), h8 = __any(rem & 8u), h4 = __any(rem & 4u), h2 = __any(rem & 2u),
+             h1 = __any(rem & 1u);
+  const uint32_t p8 = h16 ? 16 : 0, p4 = p8 + (h8 ? 8 : 0), p2 = p4 + (h4 ? 4 : 0), p1 = p2 + (h2 ? 2 : 0);
+  uint32_t t16[16], t8[8], t4[4], t2[2], t1[1];
+  if (h16) load_part<16>(t16, tail, active, zero_off);
+  if (h8) load_part<8>(t8, tail + p8, active, zero_off);
+  if (h4) load_part<4>(t4, tail + p4, active, zero_off);
+  if (h2) load_part<2>(t2, tail + p2, active, zero_off);
+  if (h1) load_part<1>(t1, tail + p1, active, zero_off);
+  if (h1) fold_part<1, LW, NHI>(c, lds_lane, t1);
+  if (h2) fold_part<2, LW, NHI>(c, lds_lane, t2);
+  if (h4) fold_part<4, LW, NHI>(c, lds_lane, t4);
+  if (h8) fold_part<8, LW, NHI>(c, lds_lane, t8);
+  if (h16) fold_part<16, LW, NHI>(c, lds_lane, t16);
   // full 32-token blocks, two at a time: the weight-32 carries of the two
   // trees meet in one full adder at plane 5, and only its carry ripples on
   uint32_t b = 0;
@@ -224,28 +251,6 @@ __device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lan
     load_block(tk, tok + b * 32);
     fold32<LW, NHI>(c, lds_lane, tk);
   }
-  // The last partial block, folded exactly as 16/8/4/2/1-token parts: part
-  // 2^k is folded when any lane's remainder has bit k, so the parts cover
-  // every lane's remainder, and a lane reads zero-row padding past its own
-  // (every token list ends with at least one padding token and is padded to
-  // a multiple of 32). The parts' token loads are all issued before the
-  // first fold so that their latencies overlap.
-  const uint32_t rem = active ? (ntok & 31u) : 0u;
-  const uint32_t* tail = active ? tok + (uint64_t)nfull * 32 : nullptr;
-  const bool h16 = __any(rem & 16u), h8 = __any(rem & 8u), h4 = __any(rem & 4u), h2 = __any(rem & 2u),
-             h1 = __any(rem & 1u);
-  const uint32_t p8 = h16 ? 16 : 0, p4 = p8 + (h8 ? 8 : 0), p2 = p4 + (h4 ? 4 : 0), p1 = p2 + (h2 ? 2 : 0);
-  uint32_t t16[16], t8[8], t4[4], t2[2], t1[1];
-  if (h16) load_part<16>(t16, tail, active, zero_off);
-  if (h8) load_part<8>(t8, tail + p8, active, zero_off);
-  if (h4) load_part<4>(t4, tail + p4, active, zero_off);
-  if (h2) load_part<2>(t2, tail + p2, active, zero_off);
-  if (h1) load_part<1>(t1, tail + p1, active, zero_off);
-  if (h16) fold_part<16, LW, NHI>(c, lds_lane, t16);
-  if (h8) fold_part<8, LW, NHI>(c, lds_lane, t8);
-  if (h4) fold_part<4, LW, NHI>(c, lds_lane, t4);
-  if (h2) fold_part<2, LW, NHI>(c, lds_lane, t2);
-  if (h1) fold_part<1, LW, NHI>(c, lds_lane, t1);
   if (!active) return;
   // K = 2^NP - T as NP all-ones/all-zeros masks, shared by the lane's words
   const uint32_t allpass = T <= 0 ? 0xFFFFFFFFu : 0u;
