@@ -24,6 +24,9 @@
  *     read length times the error tolerance e.
  *   Section 3, steps 4-5: a candidate location is checked against the bit of
  *     the bin holding its first base.
+ *   Section 1 (seed-and-extend steps 2-4): a mapper selects seeds of a read,
+ *     looks them up in an index of the reference, and gets the candidate
+ *     locations the filter then checks.
  *   Section 1 (seed-and-extend step 5) and Section 5 (evaluation metrics):
  *     a location that passes the filter is verified by aligning the read to
  *     the reference there with dynamic programming; a passing location that
@@ -47,7 +50,12 @@
  *     + q - 1, G)), with unit-cost substitutions, insertions and deletions
  *     (Levenshtein distance, free start and end in the reference); a byte
  *     other than A, C, G, T (either case) matches nothing; the location maps
- *     when that distance is at most E.
+ *     when that distance is at most E;
+ *   - seeding: seeds are the read's non-overlapping k-mers at offsets 0, k,
+ *     2k, ... whose bases are all A, C, G, T; a seed at offset o found at
+ *     reference position p votes for bin max(p - o, 0) / B; a read's
+ *     candidates are its bins ranked by votes (more first), then by bin
+ *     (smaller first), the first `cap` of them, listed by increasing bin.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -285,6 +293,119 @@ int oracle_verify(const uint8_t* ref, uint64_t G, uint32_t B, uint32_t O, uint32
     }
   }
   return bad ? -1 : 0;
+}
+
+/* One reference k-mer occurrence: code and start position. */
+typedef struct {
+  uint64_t code;
+  uint64_t pos;
+} kmer_pos;
+
+static int cmp_kmer_pos(const void* a, const void* b) {
+  const kmer_pos* x = (const kmer_pos*)a;
+  const kmer_pos* y = (const kmer_pos*)b;
+  if (x->code != y->code) return x->code < y->code ? -1 : 1;
+  if (x->pos != y->pos) return x->pos < y->pos ? -1 : 1;
+  return 0;
+}
+
+typedef struct {
+  int64_t bin;
+  uint64_t votes;
+} bin_votes;
+
+static int cmp_int64(const void* a, const void* b) {
+  const int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* more votes first, then the smaller bin */
+static int cmp_rank(const void* a, const void* b) {
+  const bin_votes* x = (const bin_votes*)a;
+  const bin_votes* y = (const bin_votes*)b;
+  if (x->votes != y->votes) return x->votes > y->votes ? -1 : 1;
+  return x->bin < y->bin ? -1 : (x->bin > y->bin ? 1 : 0);
+}
+
+static int cmp_bin(const void* a, const void* b) {
+  const bin_votes* x = (const bin_votes*)a;
+  const bin_votes* y = (const bin_votes*)b;
+  return x->bin < y->bin ? -1 : (x->bin > y->bin ? 1 : 0);
+}
+
+/* Seed-hit candidate bins of every read (the seeding steps that precede the
+ * filter). cand_off[n + 1] and cand_bin (room for n * cap entries) receive a
+ * CSR list; returns the number of candidates, or -1 on bad arguments. The
+ * reference's k-mers are listed and sorted by code, and each seed's hits are
+ * the run of its code in that list. */
+int64_t oracle_seed_candidates(const uint8_t* ref, uint64_t G, const uint8_t* bases, const int64_t* offsets,
+                               uint64_t n, uint32_t k, uint32_t B, uint32_t cap, int64_t* cand_off,
+                               int32_t* cand_bin) {
+  if (k == 0 || k > 16 || B == 0) return -1;
+  uint64_t m = 0;
+  kmer_pos* table = (kmer_pos*)malloc(sizeof(kmer_pos) * (G >= k ? G - k + 1 : 1));
+  if (!table) return -1;
+  for (uint64_t p = 0; p + k <= G; ++p) {
+    int64_t code = oracle_token_code(ref + p, k);
+    if (code < 0) continue;
+    table[m].code = (uint64_t)code;
+    table[m].pos = p;
+    ++m;
+  }
+  qsort(table, m, sizeof(kmer_pos), cmp_kmer_pos);
+  int64_t total = 0;
+  for (uint64_t r = 0; r < n; ++r) {
+    const uint8_t* rd = bases + offsets[r];
+    const int64_t L = offsets[r + 1] - offsets[r];
+    /* every hit's bin, with repeats */
+    uint64_t nh = 0, cap_h = 64;
+    int64_t* hits = (int64_t*)malloc(sizeof(int64_t) * cap_h);
+    for (int64_t o = 0; o + (int64_t)k <= L; o += k) {
+      int64_t code = oracle_token_code(rd + o, k);
+      if (code < 0) continue;
+      /* first entry with this code (binary search), then its run */
+      uint64_t lo = 0, hi = m;
+      while (lo < hi) {
+        uint64_t mid = (lo + hi) / 2;
+        if (table[mid].code < (uint64_t)code) lo = mid + 1;
+        else hi = mid;
+      }
+      for (uint64_t h = lo; h < m && table[h].code == (uint64_t)code; ++h) {
+        int64_t loc = (int64_t)table[h].pos - o;
+        if (loc < 0) loc = 0;
+        if (nh == cap_h) {
+          cap_h *= 2;
+          hits = (int64_t*)realloc(hits, sizeof(int64_t) * cap_h);
+        }
+        hits[nh++] = loc / (int64_t)B;
+      }
+    }
+    /* votes per bin */
+    qsort(hits, nh, sizeof(int64_t), cmp_int64);
+    bin_votes* bv = (bin_votes*)malloc(sizeof(bin_votes) * (nh ? nh : 1));
+    uint64_t nb_r = 0;
+    for (uint64_t i = 0; i < nh;) {
+      uint64_t j = i;
+      while (j < nh && hits[j] == hits[i]) ++j;
+      bv[nb_r].bin = hits[i];
+      bv[nb_r].votes = j - i;
+      ++nb_r;
+      i = j;
+    }
+    if (nb_r > cap) {
+      qsort(bv, nb_r, sizeof(bin_votes), cmp_rank);
+      nb_r = cap;
+      qsort(bv, nb_r, sizeof(bin_votes), cmp_bin);
+    }
+    cand_off[r] = total;
+    for (uint64_t i = 0; i < nb_r; ++i) cand_bin[total + (int64_t)i] = (int32_t)bv[i].bin;
+    total += (int64_t)nb_r;
+    free(bv);
+    free(hits);
+  }
+  cand_off[n] = total;
+  free(table);
+  return total;
 }
 
 /* Threads the parallel loops will use. */

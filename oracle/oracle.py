@@ -11,6 +11,8 @@ follows (arXiv 1708.04329):
   * max_edits          Section 6, read-existence figure caption (ceil of L*e)
   * scan_all           Section 3, steps 1-3 over every bin
   * scan_candidates    Section 3, steps 4-5 (bin of the location's first base)
+  * seed_candidates    Section 1, seed-and-extend steps 2-4 (seeds of a read,
+                       looked up in the reference, give candidate locations)
   * semiglobal_distance, verify
                        Section 1, seed-and-extend step 5 (dynamic-programming
                        alignment of the read at a location) and Section 5,
@@ -83,6 +85,8 @@ def load(path: str = _LIB):
     lib.oracle_bin_bases.restype = None
     lib.oracle_verify.argtypes = [P, U64, U32, U32, U32, P, P, U64, P, P, U32, P, P, P, P, P, I]
     lib.oracle_verify.restype = I
+    lib.oracle_seed_candidates.argtypes = [P, U64, P, P, U64, U32, U32, U32, P, P]
+    lib.oracle_seed_candidates.restype = I64
     lib.oracle_threads.argtypes = [I]
     lib.oracle_threads.restype = I
     _cache[path] = lib
@@ -225,6 +229,20 @@ class Oracle:
         if rc != 0:
             raise ValueError("candidate bin out of range")
         return dist, match
+
+    def seed_candidates(self, ref, bases, offsets, k: int, B: int, cap: int):
+        """(cand_off int64 [n+1], cand_bin int32 [n_cand]) of the seed-hit candidates."""
+        ref = _u8(ref)
+        bases = _u8(bases)
+        offs = np.ascontiguousarray(offsets, np.int64)
+        n = len(offs) - 1
+        co = np.empty(n + 1, np.int64)
+        cb = np.empty(max(1, n * cap), np.int32)
+        total = self.lib.oracle_seed_candidates(_p(ref), len(ref), _p(bases), _p(offs), n, k, B, cap, _p(co),
+                                                _p(cb))
+        if total < 0:
+            raise ValueError("bad seeding arguments")
+        return co, cb[:total].copy()
 
     def threads_used(self) -> int:
         return int(self.lib.oracle_threads(self.threads))

@@ -15,6 +15,7 @@ import tempfile
 import pytest
 
 import test_oracle_pins as pins
+import test_oracle_seed_pins as spins
 import test_oracle_verify_pins as vpins
 from oracle import Oracle
 from oracle.oracle import BUILD_CMD, _SRC
@@ -37,6 +38,13 @@ MUTANTS = {
     "verify_window_misses_last_token_bases": ("*hi = b > a ? b + q - 1 : a;", "*hi = b > a ? b : a;"),
     "verify_match_strict": ("match[k] = d <= E ? 1 : 0;", "match[k] = d < E ? 1 : 0;"),
     "verify_substitution_free": ("((rc >= 0 && rc == tc) ? 0u : 1u)", "0u"),
+    "seed_overlapping_seeds": ("o + (int64_t)k <= L; o += k)", "o + (int64_t)k <= L; o += 1)"),
+    "seed_no_clamp_at_start": ("if (loc < 0) loc = 0;\n        if (nh", "if (nh"),
+    "seed_rank_ties_to_larger_bin": ("return x->bin < y->bin ? -1 : (x->bin > y->bin ? 1 : 0);\n}\n\nstatic int cmp_bin",
+                                     "return x->bin > y->bin ? -1 : (x->bin < y->bin ? 1 : 0);\n}\n\nstatic int cmp_bin"),
+    "seed_rank_fewer_votes_first": ("if (x->votes != y->votes) return x->votes > y->votes ? -1 : 1;",
+                                    "if (x->votes != y->votes) return x->votes < y->votes ? -1 : 1;"),
+    "seed_n_seed_used": ("if (code < 0) continue;\n      /* first entry", "if (code < 0) code = 0;\n      /* first entry"),
 }
 
 PIN_CALLS = [
@@ -62,6 +70,8 @@ PIN_CALLS = [
     lambda o: vpins.test_verify_window_edges(o),
     lambda o: vpins.test_verify_truth_locations(o),
     lambda o: vpins.test_verify_mask_skips_pairs(o),
+    *[(lambda o, s=s: spins.test_seed_candidates_bruteforce(o, s)) for s in range(3)],
+    lambda o: spins.test_seed_ties_cap_and_clamp(o),
 ]
 
 
