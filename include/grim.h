@@ -205,6 +205,57 @@ int grim_verify_candidates(const grim_index* idx, const grim_reads* reads, const
                            uint16_t* dist_out, uint8_t* match_out, void* hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Seeding: the steps before the filter (Section 1, seed-and-extend steps
+ * 2-4: seeds of a read are looked up in an index of the reference, giving
+ * the candidate locations the filter then checks).
+ * ---------------------------------------------------------------------- */
+typedef struct grim_seeds grim_seeds; /* opaque; owns device memory */
+
+typedef struct {
+  uint64_t ref_len;      /* G */
+  uint32_t k;            /* seed length */
+  int32_t device;        /* HIP device ordinal holding the table */
+  uint64_t n_positions;  /* reference positions whose k bases are all A/C/G/T */
+  uint64_t table_bytes;  /* device bytes: (4^k + 1) uint64 starts + uint32 positions */
+} grim_seeds_info_t;
+
+/* Seed table of a reference: every position p whose k bases are A, C, G or
+ * T (either case), listed under its k-mer (a direct-address table of 4^k
+ * buckets).
+ *   ref, ref_len   reference bases (host, or device if ref_on_device = 1);
+ *                  ref_len < 2^32 (positions are stored as uint32)
+ *   k              seed length in [1, 14]
+ * Errors: GRIM_EINVAL, GRIM_ENOMEM, GRIM_EDEVICE. */
+int grim_seeds_build(const uint8_t* ref, uint64_t ref_len, uint32_t ref_on_device, uint32_t k, void* hip_stream,
+                     grim_seeds** out);
+int grim_seeds_info(const grim_seeds* seeds, grim_seeds_info_t* out);
+void grim_seeds_free(grim_seeds* seeds);
+
+/* Candidate bins of every read from its seed hits. Seeds are the read's
+ * non-overlapping k-mers at offsets 0, k, 2k, ... whose bases are all A, C,
+ * G, T; a seed at offset o found at reference position p votes for bin
+ * max(p - o, 0) / bin_size. A read's candidates are its bins ranked by votes
+ * (more first), then by bin (smaller first), the first `cap` of them, listed
+ * by increasing bin: a CSR list in the layout grim_filter_candidates takes.
+ *   cand_off    device, [n_reads + 1] int64, written
+ *   cand_bin    device, room for n_reads * cap int32; the first *n_cand_out
+ *               entries are written
+ *   n_cand_out  host, receives the number of candidates
+ * Reads may be on the host or the device (grim_reads.on_device); their error
+ * budgets are not used. Errors: GRIM_EINVAL, GRIM_ENOMEM (the seed hits of
+ * one read exceed 2^32), GRIM_EDEVICE. */
+int grim_seed_candidates(const grim_seeds* seeds, const grim_reads* reads, uint32_t bin_size, uint32_t cap,
+                         int64_t* cand_off, int32_t* cand_bin, uint64_t* n_cand_out, void* hip_stream);
+
+/* Reverse complement of every read (A<->T, C<->G, case kept, other bytes
+ * unchanged), read by read with the same offsets: the filter looks at the
+ * forward strand only, and a caller covers the other strand by submitting
+ * these as more reads. All pointers are device pointers; out has n_bases
+ * bytes. */
+int grim_reverse_complement(const uint8_t* bases, uint64_t n_bases, const int64_t* offsets, uint64_t n_reads,
+                            uint8_t* out, void* hip_stream);
+
+/* ------------------------------------------------------------------------
  * Batching layer: launch-shape tuning and a graph-captured steady-state loop.
  * Both drive the same kernels as grim_filter_scan / grim_filter_candidates;
  * the arithmetic (and therefore every output bit) is unchanged.

@@ -60,6 +60,14 @@ class IndexInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class SeedsInfo(ctypes.Structure):
+    _fields_ = [("ref_len", ctypes.c_uint64), ("k", ctypes.c_uint32), ("device", ctypes.c_int32),
+                ("n_positions", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class _Reads(ctypes.Structure):
     _fields_ = [("bases", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("n_reads", ctypes.c_uint64),
                 ("n_bases", ctypes.c_uint64), ("max_edits", ctypes.c_void_p), ("err_permille", ctypes.c_void_p),
@@ -129,7 +137,9 @@ EXPORTS = ["grim_abi_version", "grim_last_error", "grim_build_index", "grim_inde
            "grim_index_set_config", "grim_batcher_create", "grim_batcher_buffers", "grim_batcher_submit",
            "grim_batcher_wait", "grim_batcher_stream", "grim_batcher_free", "grim_serve_create",
            "grim_serve_submit", "grim_serve_poll", "grim_serve_wait", "grim_serve_release", "grim_serve_cancel",
-           "grim_serve_stats", "grim_serve_reset_stats", "grim_serve_destroy", "grim_verify_candidates"]
+           "grim_serve_stats", "grim_serve_reset_stats", "grim_serve_destroy", "grim_verify_candidates",
+           "grim_seeds_build", "grim_seeds_info", "grim_seeds_free", "grim_seed_candidates",
+           "grim_reverse_complement"]
 
 _lib = None
 
@@ -156,6 +166,11 @@ def lib(path: str = LIB_PATH):
         "grim_filter_scan": ([P, ctypes.POINTER(_Reads), P, P, U32, P], I),
         "grim_filter_candidates": ([P, ctypes.POINTER(_Reads), P, P, U64, P, P, P], I),
         "grim_verify_candidates": ([P, ctypes.POINTER(_Reads), P, P, U64, P, P, P, P], I),
+        "grim_seeds_build": ([P, U64, U32, U32, P, PP], I),
+        "grim_seeds_info": ([P, ctypes.POINTER(SeedsInfo)], I),
+        "grim_seeds_free": ([P], None),
+        "grim_seed_candidates": ([P, ctypes.POINTER(_Reads), U32, U32, P, P, ctypes.POINTER(ctypes.c_uint64), P], I),
+        "grim_reverse_complement": ([P, U64, P, U64, P, P], I),
         "grim_profile_enable": ([I], I),
         "grim_profile_read": ([ctypes.POINTER(Profile), I], I),
         "grim_tune": ([P, ctypes.POINTER(_Reads), P, P, U64, P, ctypes.POINTER(TuneResult)], I),
@@ -330,6 +345,67 @@ def grim_build_index(ref, bin_size: int, overlap: int, q: int, layout: int = LAY
     _check(lib().grim_build_index(_ptr(ref), len(ref), 1 if _on_device(ref) else 0, bin_size, overlap, q,
                                   layout, _stream_handle(stream), ctypes.byref(h)))
     return Index(h.value)
+
+
+class Seeds:
+    """A seed table (k-mer -> reference positions) resident on one GPU."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        out = SeedsInfo()
+        _check(lib().grim_seeds_info(self._h, ctypes.byref(out)))
+        return out.as_dict()
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib().grim_seeds_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def grim_seeds_build(ref, k: int = 12, stream=None) -> Seeds:
+    """Seed table of ``ref`` (uint8 ASCII, torch or numpy): positions of every k-mer."""
+    _check_dtype(ref, "ref", np.uint8)
+    h = ctypes.c_void_p()
+    _check(lib().grim_seeds_build(_ptr(ref), len(ref), 1 if _on_device(ref) else 0, k, _stream_handle(stream),
+                                  ctypes.byref(h)))
+    return Seeds(h.value)
+
+
+def grim_seed_candidates(seeds: Seeds, reads: ReadSet, bin_size: int, cap: int, cand_off, cand_bin,
+                         stream=None) -> int:
+    """Seed-hit candidate bins as CSR: cand_off int64 [n+1], cand_bin int32 (room for n*cap);
+    returns the number of candidates."""
+    _check_dtype(cand_off, "cand_off", np.int64)
+    _check_dtype(cand_bin, "cand_bin", np.int32)
+    n = reads._struct().n_reads
+    if len(cand_off) < n + 1 or len(cand_bin) < n * cap:
+        raise ValueError("cand_off needs n + 1 entries and cand_bin n * cap")
+    r = reads._struct()
+    total = ctypes.c_uint64()
+    _check(lib().grim_seed_candidates(seeds.handle, ctypes.byref(r), bin_size, cap, _ptr(cand_off), _ptr(cand_bin),
+                                      ctypes.byref(total), _stream_handle(stream)))
+    return int(total.value)
+
+
+def grim_reverse_complement(bases, offsets, out, stream=None):
+    """Reverse complement of every read into ``out`` (device tensors, same offsets)."""
+    _check_dtype(bases, "bases", np.uint8)
+    _check_dtype(offsets, "offsets", np.int64)
+    _check_dtype(out, "out", np.uint8)
+    _check(lib().grim_reverse_complement(_ptr(bases), len(bases), _ptr(offsets), len(offsets) - 1, _ptr(out),
+                                         _stream_handle(stream)))
 
 
 def grim_index_load(path: str, stream=None) -> Index:

@@ -92,6 +92,15 @@ def test_scan_rejects_null_arguments():
     assert L.grim_filter_scan(None, ctypes.byref(r), None, None, 0, None) == grim.GRIM_EINVAL
     assert L.grim_filter_candidates(None, ctypes.byref(r), None, None, 0, None, None, None) == grim.GRIM_EINVAL
     assert L.grim_verify_candidates(None, ctypes.byref(r), None, None, 0, None, None, None, None) == grim.GRIM_EINVAL
+    n = ctypes.c_uint64()
+    assert L.grim_seed_candidates(None, ctypes.byref(r), 2048, 8, None, None, ctypes.byref(n), None) == grim.GRIM_EINVAL
+    assert L.grim_seeds_info(None, None) == grim.GRIM_EINVAL
+    h = ctypes.c_void_p()
+    ref = (ctypes.c_uint8 * 16)(*b"ACGTACGTACGTACGT")
+    assert L.grim_seeds_build(ref, 16, 0, 0, None, ctypes.byref(h)) == grim.GRIM_EINVAL    # k = 0
+    assert L.grim_seeds_build(ref, 16, 0, 15, None, ctypes.byref(h)) == grim.GRIM_EINVAL   # k = 15
+    assert L.grim_seeds_build(None, 16, 0, 12, None, ctypes.byref(h)) == grim.GRIM_EINVAL
+    L.grim_seeds_free(None)
     assert L.grim_index_info(None, None) == grim.GRIM_EINVAL
     assert L.grim_index_read(None, 1, 0, 0, None) == grim.GRIM_EINVAL
     L.grim_index_free(None)   # ignored

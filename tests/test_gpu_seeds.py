@@ -1,0 +1,131 @@
+"""Seeding on the GPU (through the C ABI) against the oracle: the CSR
+candidate lists are integers, so the bar is bit-exact (same bins, same order,
+same offsets). Inputs carry repeats, N runs and lower case; caps below and
+above the number of voted bins; one batch or many; reads on the host or the
+device; and the reverse complement helper."""
+
+from __future__ import annotations
+
+import random
+
+import numpy as np
+import pytest
+
+import synth
+import synth.configs as C
+from gpu_util import dev, empty, host, log
+from paper_1708_04329_amd import grim
+
+pytestmark = pytest.mark.gpu
+
+
+def rand_genome(rng: random.Random, G: int) -> np.ndarray:
+    g = bytearray(rng.choice(b"ACGT") for _ in range(G))
+    for _ in range(G // 500):
+        a, L = rng.randrange(G - 300), rng.randrange(30, 300)
+        b = rng.randrange(G - L)
+        g[b:b + L] = g[a:a + L]
+    for _ in range(5):
+        p = rng.randrange(G - 10)
+        g[p:p + 6] = b"NNNNNN"
+    p = rng.randrange(G - 500)
+    g[p:p + 500] = bytes(g[p:p + 500]).lower()
+    return np.frombuffer(bytes(g), np.uint8).copy()
+
+
+def rand_reads(rng: random.Random, ref: np.ndarray, n: int):
+    seqs = []
+    for _ in range(n):
+        L = rng.randrange(1, 260)
+        p = rng.randrange(len(ref) - L)
+        s = bytearray(ref[p:p + L].tobytes())
+        for _ in range(rng.randrange(0, 4)):
+            s[rng.randrange(L)] = rng.choice(b"ACGTN")
+        seqs.append(bytes(s))
+    return synth.reads_from_strings(seqs)
+
+
+def gpu_candidates(seeds, rd, B, cap, on_device=True):
+    import torch
+    n = rd.n
+    co = empty((n + 1,), torch.int64)
+    cb = empty((max(1, n * cap),), torch.int32)
+    conv = dev if on_device else (lambda a: np.ascontiguousarray(a))
+    total = grim.grim_seed_candidates(seeds, grim.ReadSet(conv(rd.bases), conv(rd.offsets)), B, cap, co, cb)
+    torch.cuda.synchronize()
+    return host(co), host(cb)[:total]
+
+
+@pytest.mark.parametrize("k,B,cap", [(6, 1000, 3), (8, 777, 50), (12, 2048, 256)])
+def test_seed_candidates_match_oracle_random(oracle, k, B, cap):
+    rng = random.Random(900 + k)
+    ref = rand_genome(rng, 200_000)
+    rd = rand_reads(rng, ref, 400)
+    seeds = grim.grim_seeds_build(dev(ref), k)
+    info = seeds.info()
+    assert info["k"] == k and info["n_positions"] > 0
+    got = gpu_candidates(seeds, rd, B, cap)
+    want = oracle.seed_candidates(ref, rd.bases, rd.offsets, k, B, cap)
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+    # host-resident reads give the same lists
+    got_h = gpu_candidates(seeds, rd, B, cap, on_device=False)
+    assert np.array_equal(got_h[0], want[0]) and np.array_equal(got_h[1], want[1])
+
+
+def test_seed_candidates_many_batches(oracle, monkeypatch):
+    rng = random.Random(5)
+    ref = rand_genome(rng, 100_000)
+    rd = rand_reads(rng, ref, 300)
+    seeds = grim.grim_seeds_build(dev(ref), 6)
+    want = oracle.seed_candidates(ref, rd.bases, rd.offsets, 6, 500, 7)
+    for limit in ("1", "700", "5000"):
+        monkeypatch.setenv("GRIM_SEED_BATCH_KEYS", limit)
+        got = gpu_candidates(seeds, rd, 500, 7)
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), limit
+
+
+@pytest.mark.parametrize("key", ["c2", "c4"])
+def test_seed_candidates_recipes(oracle, key):
+    """The candidate workloads' recipes (uniform + 1.5% repeats, cap 256; 45% repeats,
+    uneven reads, cap 1024) on small genomes: GPU == oracle == input generator."""
+    w = C.shrink(C.workload(key), genome_len=4_000_000, n_reads=4000)
+    if key == "c4":
+        w.genome.repeat_frac = 0.45
+    ref = synth.genome(w.genome)
+    rd = synth.reads(w.reads, ref)
+    seeds = grim.grim_seeds_build(dev(ref), w.cand_k)
+    got = gpu_candidates(seeds, rd, w.bin_size, w.cand_cap)
+    want = oracle.seed_candidates(ref, rd.bases, rd.offsets, w.cand_k, w.bin_size, w.cand_cap)
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+    gen = synth.candidates(ref, rd, w.bin_size, w.cand_cap, w.cand_k)
+    assert np.array_equal(got[0], gen[0]) and np.array_equal(got[1], gen[1])
+    log(key, "candidates", len(got[1]))
+
+
+def test_reverse_complement():
+    import torch
+    seqs = [b"ACGTN", b"aacgT", b"", b"GGGCCCATN-x"]
+    rd = synth.reads_from_strings(seqs)
+    out = empty((max(1, len(rd.bases)),), torch.uint8)
+    grim.grim_reverse_complement(dev(rd.bases), dev(rd.offsets), out)
+    torch.cuda.synchronize()
+    got = host(out)[:len(rd.bases)].tobytes()
+    comp = bytes.maketrans(b"ACGTacgt", b"TGCAtgca")
+    want = b"".join(s.translate(comp)[::-1] for s in seqs)
+    assert got == want
+
+
+def test_seed_errors():
+    import torch
+    ref = rand_genome(random.Random(1), 5000)
+    seeds = grim.grim_seeds_build(dev(ref), 8)
+    rd = synth.reads_from_strings([ref[10:60].tobytes()])
+    co = empty((2,), torch.int64)
+    cb = empty((8,), torch.int32)
+    with pytest.raises(grim.GrimError):
+        grim.grim_seed_candidates(seeds, grim.ReadSet(dev(rd.bases), dev(rd.offsets)), 0, 8, co, cb)
+    with pytest.raises(grim.GrimError):
+        grim.grim_seeds_build(dev(ref[:5]), 8)
+    # still usable
+    n = grim.grim_seed_candidates(seeds, grim.ReadSet(dev(rd.bases), dev(rd.offsets)), 1000, 8, co, cb)
+    assert n >= 1 and 0 in host(cb)[:n].tolist()
