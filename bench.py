@@ -83,6 +83,8 @@ def parse():
                    help="directory where the synthetic seed-hit candidate lists are saved and reused "
                         "(saves minutes of host work when the same workload is run repeatedly)")
     p.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    p.add_argument("--no-seeding", action="store_true",
+                   help="candidate workloads: skip generating the candidate lists on the GPU")
     p.add_argument("--no-verify", action="store_true",
                    help="candidate workloads: skip aligning the passing pairs after the filter")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
@@ -131,10 +133,12 @@ def main():
             os.makedirs(args.input_cache, exist_ok=True)
             cache = os.path.join(args.input_cache, f"{w.name}_g{len(ref)}_r{rd.n}_b{w.bin_size}_k{w.cand_k}"
                                                     f"_cap{w.cand_cap}")
+        cpu_seed_s = None
         if cache and os.path.exists(cache + "_cb.npy"):
             cand = (np.load(cache + "_co.npy"), np.load(cache + "_cb.npy", mmap_mode="c"))
         else:
             cand = synth.candidates(ref, rd, w.bin_size, w.cand_cap, w.cand_k)
+            cpu_seed_s = time.time() - t0
             if cache:
                 np.save(cache + "_co.npy", cand[0])
                 np.save(cache + "_cb.npy", cand[1])
@@ -269,6 +273,11 @@ def main():
                                            else (cnt, pas))
     if w.mode == "candidates" and not args.no_verify:
         out["verify"] = verify_leg(args, w, ref, rd, me, ep, reads, idx, cand, d_co, d_cb, pas, stream)
+    if w.mode == "candidates" and not args.no_seeding:
+        del cnt, pas
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out["seeding"] = seeding_leg(args, w, ref, rd, d_bases, d_offs, d_co, d_cb, cpu_seed_s, stream)
     if w.mode == "allbins" and args.serve_seconds > 0:
         del mask
         torch.cuda.synchronize()
@@ -356,6 +365,42 @@ def verify_leg(args, w, ref, rd, me, ep, reads, idx, cand, d_co, d_cb, pas, stre
         log(f"verify oracle: {int(mask.sum())} pairs in {dt:.1f}s; GPU bit-exact: "
             f"{res['cpu_oracle']['gpu_bit_exact_on_sample']}")
     return res
+
+
+def seeding_leg(args, w, ref, rd, d_bases, d_offs, d_co, d_cb, cpu_seed_s, stream):
+    """Generate the workload's candidate lists on the GPU (seed table, then seed-hit votes) and
+    compare them with the lists the input generator produced on the host."""
+    import torch
+    from paper_1708_04329_amd import grim
+    dref = torch.from_numpy(ref).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seeds = grim.grim_seeds_build(dref, w.cand_k, stream)
+    torch.cuda.synchronize()
+    table_ms = (time.perf_counter() - t0) * 1e3
+    del dref
+    n = rd.n
+    co = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    cb = torch.empty(n * w.cand_cap, dtype=torch.int32, device="cuda")
+    rs = grim.ReadSet(d_bases, d_offs)
+    total = grim.grim_seed_candidates(seeds, rs, w.bin_size, w.cand_cap, co, cb, stream)   # warm-up
+    times = []
+    for _ in range(max(1, min(args.steps, 3))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        total = grim.grim_seed_candidates(seeds, rs, w.bin_size, w.cand_cap, co, cb, stream)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ms = min(times) * 1e3
+    same = bool(total == len(d_cb) and torch.equal(co, d_co) and torch.equal(cb[:total], d_cb[:total]))
+    info = seeds.info()
+    seeds.free()
+    del co, cb
+    log(f"seeding: table {table_ms:.0f} ms; {total:,} candidates for {n:,} reads in {ms:.0f} ms "
+        f"({n / (ms * 1e-3):.3g} reads/s); equal to the host generator: {same}")
+    return {"table_build_ms": table_ms, "table_bytes": info["table_bytes"], "candidates_ms": ms,
+            "reads_per_s": n / (ms * 1e-3), "n_candidates": total, "equal_to_input_generator": same,
+            "input_generator_s": cpu_seed_s, "input_generator_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)) if cpu_seed_s else None}
 
 
 def request_stream(seconds: float, rate: float, pool_n: int, seed: int, size_max: int = 20000):
