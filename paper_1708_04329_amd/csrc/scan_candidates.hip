@@ -13,11 +13,11 @@
 // of one bin vector per pair is the compulsory traffic of this mode.
 //
 // Two lane layouts: one lane per pair (the lane streams the whole vector), or
-// a group of G = VW/16 lanes per pair, each lane streaming 64 contiguous bytes
+// a group of G lanes per pair, each lane streaming 32 (q = 5) or 64 contiguous bytes
 // of the vector (so one wavefront load touches 64/G vectors instead of 64
 // scattered ones) with its slice of the planes kept in registers for all of
-// the read's pairs, and the partial counts summed across the group with
-// xor-shuffles.
+// the read's pairs, and the partial counts summed across the group with DPP
+// moves.
 //
 // Two launch shapes: one wavefront per read (the hardware dispatcher
 // balances), or a persistent grid whose wavefronts take the next read from an
@@ -176,32 +176,35 @@ __device__ __forceinline__ void cand_read(const CandArgs& a, uint64_t r, uint64_
   wave_sync();
 }
 
-// Cooperative layout: G = VW / 16 lanes per pair, lane j streams words
-// [16j, 16j + 16) of the bin's vector and keeps the same words of the first
-// four planes in registers for all of the read's pairs.
+// Cooperative layout: G = VW / WPL lanes per pair, lane j streams words
+// [WPL j, WPL j + WPL) of the bin's vector and keeps the same words of the
+// first four planes in registers for all of the read's pairs. WPL is 8 for
+// 32-word vectors (q = 5: fewer registers, more wavefronts in flight for the
+// short candidate lists of that mode) and 16 above.
 template <int VW>
 __device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, uint64_t n_cand, uint32_t* hist,
                                                uint32_t* planes, uint32_t lane) {
-  constexpr int G = VW / 16;
-  constexpr int PPW = 64 / G;  // pairs per wavefront pass
+  constexpr int WPL = VW <= 32 ? 8 : 16;  // words of the vector per lane
+  constexpr int G = VW / WPL;              // lanes per pair
+  constexpr int PPW = 64 / G;              // pairs per wavefront pass
   int64_t c0 = 0, c1 = 0;
   const int Ki = build_planes<VW>(a, r, n_cand, hist, planes, lane, &c0, &c1);
   if (Ki < 0) return;
   const uint32_t K = (uint32_t)Ki;
   const int32_t T = a.thr[r];
   const uint32_t j = lane % G, g = lane / G;
-  uint32_t pl[4][16];
+  uint32_t pl[4][WPL];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if ((uint32_t)k < K) {
 #pragma unroll
-      for (int w4 = 0; w4 < 4; ++w4) {
-        const uint4 p = reinterpret_cast<const uint4*>(planes + k * VW + 16 * j)[w4];
+      for (int w4 = 0; w4 < WPL / 4; ++w4) {
+        const uint4 p = reinterpret_cast<const uint4*>(planes + k * VW + WPL * j)[w4];
         pl[k][4 * w4 + 0] = p.x; pl[k][4 * w4 + 1] = p.y; pl[k][4 * w4 + 2] = p.z; pl[k][4 * w4 + 3] = p.w;
       }
     } else {
 #pragma unroll
-      for (int w = 0; w < 16; ++w) pl[k][w] = 0;
+      for (int w = 0; w < WPL; ++w) pl[k][w] = 0;
     }
   }
   // U pair-passes per iteration: their bin ids, then their vectors, are
@@ -216,13 +219,13 @@ __device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, ui
       c[u] = cb + u * PPW + g;
       x[u] = c[u] < c1 ? a.cand_bin[c[u]] : 0;
     }
-    uint32_t v[U][16];
+    uint32_t v[U][WPL];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       ok[u] = c[u] < c1 && x[u] >= 0 && (uint64_t)x[u] < a.nb;
-      const uint4* v4 = reinterpret_cast<const uint4*>(a.bm + (uint64_t)(ok[u] ? x[u] : 0) * VW + 16 * j);
+      const uint4* v4 = reinterpret_cast<const uint4*>(a.bm + (uint64_t)(ok[u] ? x[u] : 0) * VW + WPL * j);
 #pragma unroll
-      for (int w4 = 0; w4 < 4; ++w4) {
+      for (int w4 = 0; w4 < WPL / 4; ++w4) {
         uint4 t = make_uint4(0, 0, 0, 0);
         if (ok[u]) t = v4[w4];
         v[u][4 * w4 + 0] = t.x; v[u][4 * w4 + 1] = t.y; v[u][4 * w4 + 2] = t.z; v[u][4 * w4 + 3] = t.w;
@@ -236,13 +239,13 @@ __device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, ui
         if ((uint32_t)k < K) {  // wave-uniform
           uint32_t acc = 0;
 #pragma unroll
-          for (int w = 0; w < 16; ++w) acc += __popc(v[u][w] & pl[k][w]);
+          for (int w = 0; w < WPL; ++w) acc += __popc(v[u][w] & pl[k][w]);
           part += acc << k;
         }
       }
       for (uint32_t k = 4; k < K; ++k) {  // rare: a token repeated 16 times or more
         uint32_t acc = 0;
-        for (int w = 0; w < 16; ++w) acc += __popc(v[u][w] & planes[k * VW + 16 * j + w]);
+        for (int w = 0; w < WPL; ++w) acc += __popc(v[u][w] & planes[k * VW + WPL * j + w]);
         part += acc << k;
       }
       part = group_sum<G>(part);  // the group's partial counts (groups are aligned runs of G lanes)
@@ -280,13 +283,16 @@ __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
     const uint64_t r = (uint64_t)blockIdx.x * NW + wave;
     if (r < n_reads) one(r);
   } else {
-    // every wavefront leaves once the counter has passed n_reads
+    // every wavefront leaves once the counter has passed n_reads; reads are
+    // taken kGrab at a time so the counter sees few atomics
+    constexpr uint32_t kGrab = 8;
     while (true) {
-      uint32_t r = 0;
-      if (lane == 0) r = atomicAdd(a.work, 1u);
-      r = __shfl(r, 0);
-      if ((uint64_t)r >= n_reads) break;
-      one(r);
+      uint32_t r0 = 0;
+      if (lane == 0) r0 = atomicAdd(a.work, kGrab);
+      r0 = __shfl(r0, 0);
+      if ((uint64_t)r0 >= n_reads) break;
+      const uint64_t r1 = min((uint64_t)r0 + kGrab, n_reads);
+      for (uint64_t r = r0; r < r1; ++r) one(r);
     }
   }
 }
