@@ -498,9 +498,9 @@ extern "C" int grim_serve_create(const grim_index* idx, const grim_serve_config*
   if (c.policy > GRIM_SERVE_PLAIN) return set_error(GRIM_EINVAL, "bad policy");
   if (c.flags & ~GRIM_READS_ALLOW_SHORT_OVERLAP) return set_error(GRIM_EINVAL, "unknown flags");
   if (!c.max_inflight) c.max_inflight = 64;
-  if (!c.max_batch_reads) c.max_batch_reads = 16384;
-  if (!c.slice_reads) c.slice_reads = 4096;
-  if (!c.n_streams) c.n_streams = 4;
+  if (!c.max_batch_reads) c.max_batch_reads = 65536;
+  if (!c.slice_reads) c.slice_reads = 16384;
+  if (!c.n_streams) c.n_streams = 2;
   if (!c.max_request_reads) c.max_request_reads = 65536;
   if (!c.host_arena_bytes) c.host_arena_bytes = 1ull << 30;
   if (c.max_inflight > 4096 || c.n_streams > 16 || c.max_batch_reads > (1u << 22) || c.max_request_reads > (1u << 22))
