@@ -5,7 +5,7 @@
 // The count with multiplicity, sum_i bit[x][t_i], is rewritten as
 // sum_j 2^j * popcount(vec_x AND plane_j), where plane_j is the 4^q-bit set of
 // tokens whose number of occurrences in the read has bit j set. One
-// wavefront handles one read: it builds the read's token histogram and its
+// wavefront handles one read: it counts the read's tokens straight into its
 // multiplicity planes in LDS once, then each lane takes one candidate bin,
 // streams that bin's vector (128 B at q=5, 512 B at q=6) from HBM with
 // 16-byte loads and ANDs it with the planes (read from LDS with a
@@ -52,13 +52,20 @@ __device__ __forceinline__ uint32_t group_sum(uint32_t x) {
   return x;
 }
 
-// Steps 1-3 for read r: histogram of its tokens and the K multiplicity planes
-// in this wavefront's LDS. Returns K, or -1 when the read has no candidates.
+// Steps 1-3 for read r: the K multiplicity planes of its tokens in this
+// wavefront's LDS, counted directly in bit-sliced form. Adding one occurrence
+// of token t flips bit t of plane 0 with an atomic XOR; if the bit was set,
+// the carry flips bit t of plane 1, and so on. The flips of one level commute,
+// and level k + 1 is flipped once per 1 -> 0 transition of level k, i.e.
+// floor(n_k / 2) times whatever the order of the lanes' atomics, so the planes
+// end up holding every token's count in binary. K, the bit length of the
+// largest count, is one more than the highest level any increment reached.
+// Returns K, or -1 when the read has no candidates.
 template <int VW>
-__device__ __forceinline__ int build_planes(const CandArgs& a, uint64_t r, uint64_t n_cand, uint32_t* hist,
-                                            uint32_t* planes, uint32_t lane, int64_t* pc0, int64_t* pc1) {
-  static_assert(VW <= 512, "token histogram of 4^q counters");
-  constexpr uint32_t kHistWords = VW * 16;  // R4 / 2 packed uint16 counters (R4 = 32*VW)
+__device__ __forceinline__ int build_planes(const CandArgs& a, uint64_t r, uint64_t n_cand, uint32_t* planes,
+                                            uint32_t lane, int64_t* pc0, int64_t* pc1) {
+  static_assert(VW <= 512, "planes of 4^q bits");
+  constexpr uint32_t kWords = kMaxPlanes * VW;
   const int64_t c0 = a.cand_off[r], c1 = a.cand_off[r + 1];
   if (c0 < 0 || c1 < c0 || (uint64_t)c1 > n_cand) {
     if (lane == 0) atomicOr(a.status, ST_BAD_CAND_OFF);
@@ -72,59 +79,30 @@ __device__ __forceinline__ int build_planes(const CandArgs& a, uint64_t r, uint6
   const uint32_t* tok = a.tokens + token_base(o0, r);
   const uint32_t R4 = a.R4;
 
-  // 1. token histogram (uint16 counters packed in pairs)
-  for (uint32_t i = lane; i < kHistWords; i += 64) hist[i] = 0;
+  uint4* p4 = reinterpret_cast<uint4*>(planes);  // kWords = 16 VW, a multiple of 4
+  for (uint32_t i = lane; i < kWords / 4; i += 64) p4[i] = make_uint4(0, 0, 0, 0);
   wave_sync();
+  uint32_t top = 0;  // highest level reached + 1
   for (uint32_t i = lane; i < ntok; i += 64) {
     const uint32_t t = tok[i];
-    if (t < R4) atomicAdd(&hist[t >> 1], 1u << ((t & 1u) * 16));
+    if (t >= R4) continue;
+    const uint32_t bit = 1u << (t & 31u);
+    uint32_t* w = planes + (t >> 5);
+    uint32_t k = 0;
+    // a count stays below 2^16 (at most 65535 tokens), so k stays below kMaxPlanes
+    while ((atomicXor(w + k * VW, bit) & bit) && k + 1 < (uint32_t)kMaxPlanes) ++k;
+    top = max(top, k + 1);
   }
+  for (int off = 32; off >= 1; off >>= 1) top = max(top, (uint32_t)__shfl_xor((int)top, off));
   wave_sync();
-  // 2. number of planes = bit length of the largest multiplicity
-  uint32_t mx = 0;
-  for (uint32_t i = lane; i < kHistWords; i += 64) {
-    const uint32_t h = hist[i];
-    mx = max(mx, max(h & 0xFFFFu, h >> 16));
-  }
-  for (int off = 32; off >= 1; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
-  const uint32_t K = mx ? 32u - __clz(mx) : 0u;
-  // 3. planes: bit b of plane j word w = bit j of the count of token 32*w + b.
-  // The planes overwrite the histogram (same LDS), so every lane first takes
-  // its words' counts into registers.
-  constexpr int kWL = VW >= 64 ? VW / 64 : 1;  // words of the vector per lane
-  uint32_t m2[kWL][16];                        // counts of tokens 32w .. 32w+31, two per word
-#pragma unroll
-  for (int i = 0; i < kWL; ++i) {
-    const uint32_t w = lane + 64u * i;
-    if (w < VW) {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) m2[i][k] = hist[w * 16 + k];
-    }
-  }
-  wave_sync();
-#pragma unroll
-  for (int i = 0; i < kWL; ++i) {
-    const uint32_t w = lane + 64u * i;
-    if (w >= VW) continue;
-    for (uint32_t j = 0; j < K; ++j) {
-      uint32_t pw = 0;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        pw |= ((m2[i][k] >> j) & 1u) << (2 * k);
-        pw |= ((m2[i][k] >> (16 + j)) & 1u) << (2 * k + 1);
-      }
-      planes[j * VW + w] = pw;
-    }
-  }
-  wave_sync();
-  return (int)K;
+  return (int)top;
 }
 
 template <int VW>
-__device__ __forceinline__ void cand_read(const CandArgs& a, uint64_t r, uint64_t n_cand, uint32_t* hist,
+__device__ __forceinline__ void cand_read(const CandArgs& a, uint64_t r, uint64_t n_cand,
                                           uint32_t* planes, uint32_t lane) {
   int64_t c0 = 0, c1 = 0;
-  const int Ki = build_planes<VW>(a, r, n_cand, hist, planes, lane, &c0, &c1);
+  const int Ki = build_planes<VW>(a, r, n_cand, planes, lane, &c0, &c1);
   if (Ki < 0) return;
   const uint32_t K = (uint32_t)Ki;
   const int32_t T = a.thr[r];
@@ -182,13 +160,13 @@ __device__ __forceinline__ void cand_read(const CandArgs& a, uint64_t r, uint64_
 // 32-word vectors (q = 5: fewer registers, more wavefronts in flight for the
 // short candidate lists of that mode) and 16 above.
 template <int VW>
-__device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, uint64_t n_cand, uint32_t* hist,
+__device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, uint64_t n_cand,
                                                uint32_t* planes, uint32_t lane) {
   constexpr int WPL = VW <= 32 ? 8 : 16;  // words of the vector per lane
   constexpr int G = VW / WPL;              // lanes per pair
   constexpr int PPW = 64 / G;              // pairs per wavefront pass
   int64_t c0 = 0, c1 = 0;
-  const int Ki = build_planes<VW>(a, r, n_cand, hist, planes, lane, &c0, &c1);
+  const int Ki = build_planes<VW>(a, r, n_cand, planes, lane, &c0, &c1);
   if (Ki < 0) return;
   const uint32_t K = (uint32_t)Ki;
   const int32_t T = a.thr[r];
@@ -264,20 +242,17 @@ __device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, ui
 
 template <int VW, int NW, bool PERSISTENT, bool COOP>
 __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
-  // one region per wavefront: the token histogram (4^q uint16 counters),
-  // then, in the same words, the multiplicity planes (kMaxPlanes x VW words)
-  constexpr uint32_t kPerWave = VW * 16;
-  static_assert(kMaxPlanes * VW <= kPerWave, "planes fit the histogram's words");
+  // one region per wavefront: the multiplicity planes (kMaxPlanes x VW words)
+  constexpr uint32_t kPerWave = kMaxPlanes * VW;
   __shared__ __attribute__((aligned(16))) uint32_t lds[NW * kPerWave];
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-  uint32_t* hist = lds + wave * kPerWave;
-  uint32_t* planes = hist;
+  uint32_t* planes = lds + wave * kPerWave;
   const uint64_t n_reads = a.dyn ? min(a.dyn->n_reads, a.n_reads) : a.n_reads;
   const uint64_t n_cand = a.dyn ? min(a.dyn->n_cand, a.n_cand) : a.n_cand;
   if (a.status[0] & ~(uint32_t)(ST_BAD_BIN | ST_BAD_CAND_OFF)) return;  // rejected reads
   auto one = [&](uint64_t r) {
-    if constexpr (COOP) cand_read_coop<VW>(a, r, n_cand, hist, planes, lane);
-    else cand_read<VW>(a, r, n_cand, hist, planes, lane);
+    if constexpr (COOP) cand_read_coop<VW>(a, r, n_cand, planes, lane);
+    else cand_read<VW>(a, r, n_cand, planes, lane);
   };
   if constexpr (!PERSISTENT) {
     const uint64_t r = (uint64_t)blockIdx.x * NW + wave;
