@@ -247,11 +247,33 @@ void grim_seeds_free(grim_seeds* seeds);
 int grim_seed_candidates(const grim_seeds* seeds, const grim_reads* reads, uint32_t bin_size, uint32_t cap,
                          int64_t* cand_off, int32_t* cand_bin, uint64_t* n_cand_out, void* hip_stream);
 
+/* Per-read summary of pass masks, for a consumer that keeps the masks in
+ * device memory and copies back only a few bytes per read (a read's row is
+ * 189 KB at human scale; the masks are the filter's output, Section 3 steps
+ * 4-5). For row r of mask, mask_words uint32 words in the layout
+ * grim_filter_scan writes (bins past n_bins zero):
+ *   pass_count_out[r] = the number of set bits, i.e. of passing bins;
+ *   digest_out[r]     = sum over words i of mix64((i << 32) | row[i]), mod 2^64,
+ * with mix64 the SplitMix64 output function (Steele, Lea and Flood 2014):
+ *   z ^= z >> 30; z *= 0xBF58476D1CE4E5B9; z ^= z >> 27;
+ *   z *= 0x94D049BB133111EB; z ^= z >> 31.
+ * Every bit and its position enter the digest, so rows with equal digests are
+ * equal with high probability (not certainty).
+ *   mask            device, [n_reads][mask_words] uint32, 4-byte aligned
+ *   pass_count_out  device, [n_reads] uint32, or NULL
+ *   digest_out      device, [n_reads] uint64, or NULL
+ * Asynchronous on hip_stream. Errors: GRIM_EINVAL (NULL or misaligned mask,
+ * mask_words 0 or >= 2^32), GRIM_EDEVICE. */
+int grim_mask_summary(const uint32_t* mask, uint64_t n_reads, uint64_t mask_words, uint32_t* pass_count_out,
+                      uint64_t* digest_out, void* hip_stream);
+
 /* Reverse complement of every read (A<->T, C<->G, case kept, other bytes
  * unchanged), read by read with the same offsets: the filter looks at the
  * forward strand only, and a caller covers the other strand by submitting
  * these as more reads. All pointers are device pointers; out has n_bases
- * bytes. */
+ * bytes. Errors: GRIM_EINVAL (a NULL pointer, or offsets out of order or
+ * outside [0, n_bases]: such reads are left unwritten, the others are
+ * complemented), GRIM_ENOMEM, GRIM_EDEVICE. */
 int grim_reverse_complement(const uint8_t* bases, uint64_t n_bases, const int64_t* offsets, uint64_t n_reads,
                             uint8_t* out, void* hip_stream);
 

@@ -18,6 +18,10 @@ follows (arXiv 1708.04329):
                        alignment of the read at a location) and Section 5,
                        evaluation metrics (a passing location either yields a
                        mapping or counts against the filter)
+  * mask_summary       per read, the number of bins that pass (Section 3, step 3
+                       outcome) and a digest of the packed row: a library
+                       convention, not the paper's; mix64 is the SplitMix64
+                       output function (Steele, Lea and Flood 2014)
 """
 
 from __future__ import annotations
@@ -177,6 +181,37 @@ class Oracle:
         self.lib.oracle_scan_all(_p(bits), nb, q, _p(bases), _p(offs), n, _p(me), _p(ep),
                                  err_permille, _p(counts), _p(pas), self.threads)
         return counts, pas
+
+    @staticmethod
+    def mix64(z):
+        """SplitMix64's output function on uint64 values (wrapping arithmetic)."""
+        z = np.asarray(z, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+            return z ^ (z >> np.uint64(31))
+
+    @staticmethod
+    def pack_rows(passed: np.ndarray) -> np.ndarray:
+        """Pass matrix [n, nb] -> uint32 words [n, ceil(nb/32)], bit x % 32 of word x // 32."""
+        n, nb = passed.shape
+        W = (nb + 31) // 32
+        words = np.zeros((n, W), dtype=np.uint64)
+        for x in range(nb):
+            words[:, x // 32] |= passed[:, x].astype(np.uint64) << np.uint64(x % 32)
+        return words.astype(np.uint32)
+
+    def mask_summary(self, passed: np.ndarray):
+        """(pass count uint32 [n], digest uint64 [n]) of a pass matrix [n, nb]:
+        the count of passing bins, and the sum over the packed row's words i of
+        mix64((i << 32) | word_i), modulo 2^64."""
+        passed = np.asarray(passed).astype(bool)
+        counts = passed.sum(axis=1).astype(np.uint32)
+        words = self.pack_rows(passed).astype(np.uint64)
+        idx = np.arange(words.shape[1], dtype=np.uint64) << np.uint64(32)
+        with np.errstate(over="ignore"):
+            digests = self.mix64(words | idx[None, :]).sum(axis=1, dtype=np.uint64)
+        return counts, digests
 
     def scan_candidates(self, bits: np.ndarray, q: int, bases, offsets, cand_off, cand_bin,
                         max_edits=None, err_pm_per_read=None, err_permille: int = 0):

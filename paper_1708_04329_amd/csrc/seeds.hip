@@ -283,11 +283,17 @@ __global__ __launch_bounds__(256) void k_seed_select(CandArgs2 a) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_revcomp(const uint8_t* in, const int64_t* offsets, uint64_t n, uint8_t* out) {
+__global__ __launch_bounds__(256) void k_revcomp(const uint8_t* in, uint64_t n_bases, const int64_t* offsets, uint64_t n,
+                                                  uint8_t* out, uint32_t* bad) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t r = wave_uniform((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
   if (r >= n) return;
-  const int64_t o0 = offsets[r], L = offsets[r + 1] - o0;
+  const int64_t o0 = offsets[r], o1 = offsets[r + 1];
+  if (o0 < 0 || o1 < o0 || (uint64_t)o1 > n_bases) {  // leave the read alone, flag the call
+    if (lane == 0) atomicOr(bad, 1u);
+    return;
+  }
+  const int64_t L = o1 - o0;
   for (int64_t i = lane; i < L; i += 64) {
     const uint8_t c = in[o0 + L - 1 - i];
     uint8_t d = c;
@@ -600,12 +606,23 @@ int grim_reverse_complement(const uint8_t* bases, uint64_t n_bases, const int64_
                             uint8_t* out, void* hip_stream) {
   clear_error();
   if (n_reads == 0) return GRIM_OK;
-  if (!bases || !offsets || !out) return set_error(GRIM_EINVAL, "NULL argument");
-  (void)n_bases;
+  if (!offsets || !out || (n_bases && !bases)) return set_error(GRIM_EINVAL, "NULL argument");
+  if (n_reads > (1ull << 36)) return set_error(GRIM_EINVAL, "too many reads");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  hipLaunchKernelGGL(k_revcomp, dim3((unsigned)((n_reads + 3) / 4)), dim3(256), 0, s, bases, offsets, n_reads, out);
-  GRIM_HIP_TRY(hipGetLastError());
-  GRIM_HIP_TRY(hipStreamSynchronize(s));
+  uint32_t* bad = nullptr;  // set by the kernel when a read's offsets are out of order or out of range
+  GRIM_HIP_TRY(hipMalloc(&bad, sizeof(uint32_t)));
+  uint32_t bad_host = 0;
+  hipError_t e = hipMemsetAsync(bad, 0, sizeof(uint32_t), s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_revcomp, dim3((unsigned)((n_reads + 3) / 4)), dim3(256), 0, s, bases, n_bases, offsets,
+                       n_reads, out, bad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad_host, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(bad);
+  GRIM_HIP_TRY(e);
+  if (bad_host) return set_error(GRIM_EINVAL, "offsets out of order or outside [0, n_bases]; those reads were not written");
   return GRIM_OK;
 }
 

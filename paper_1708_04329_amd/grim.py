@@ -139,7 +139,7 @@ EXPORTS = ["grim_abi_version", "grim_last_error", "grim_build_index", "grim_inde
            "grim_serve_submit", "grim_serve_poll", "grim_serve_wait", "grim_serve_release", "grim_serve_cancel",
            "grim_serve_stats", "grim_serve_reset_stats", "grim_serve_destroy", "grim_verify_candidates",
            "grim_seeds_build", "grim_seeds_info", "grim_seeds_free", "grim_seed_candidates",
-           "grim_reverse_complement"]
+           "grim_reverse_complement", "grim_mask_summary"]
 
 _lib = None
 
@@ -171,6 +171,7 @@ def lib(path: str = LIB_PATH):
         "grim_seeds_free": ([P], None),
         "grim_seed_candidates": ([P, ctypes.POINTER(_Reads), U32, U32, P, P, ctypes.POINTER(ctypes.c_uint64), P], I),
         "grim_reverse_complement": ([P, U64, P, U64, P, P], I),
+        "grim_mask_summary": ([P, U64, U64, P, P, P], I),
         "grim_profile_enable": ([I], I),
         "grim_profile_read": ([ctypes.POINTER(Profile), I], I),
         "grim_tune": ([P, ctypes.POINTER(_Reads), P, P, U64, P, ctypes.POINTER(TuneResult)], I),
@@ -237,7 +238,7 @@ def _check_dtype(x, name, np_dtype):
     if _is_torch(x):
         import torch
         want = {np.uint8: torch.uint8, np.int64: torch.int64, np.uint16: torch.uint16, np.int32: torch.int32,
-                np.uint32: torch.uint32}[np_dtype]
+                np.uint32: torch.uint32, np.uint64: torch.uint64}[np_dtype]
         if x.dtype != want:
             raise TypeError(f"{name} must be {want}, got {x.dtype}")
     elif x.dtype != np_dtype:
@@ -406,6 +407,29 @@ def grim_reverse_complement(bases, offsets, out, stream=None):
     _check_dtype(out, "out", np.uint8)
     _check(lib().grim_reverse_complement(_ptr(bases), len(bases), _ptr(offsets), len(offsets) - 1, _ptr(out),
                                          _stream_handle(stream)))
+
+
+def grim_mask_summary(mask, pass_count=None, digest=None, stream=None):
+    """Per-read pass counts (uint32) and digests (uint64) of a [n][mask_words]
+    uint32 device mask, written into the given device tensors (asynchronous)."""
+    if not _is_torch(mask) or not mask.is_cuda:
+        raise TypeError("mask must be a device tensor")
+    _check_dtype(mask, "mask", np.uint32)
+    if mask.dim() != 2:
+        raise ValueError("mask must be [n_reads][mask_words]")
+    if not mask.is_contiguous():
+        raise ValueError("mask must be contiguous")
+    n, W = int(mask.shape[0]), int(mask.shape[1])
+    if pass_count is not None:
+        _check_dtype(pass_count, "pass_count", np.uint32)
+        if pass_count.numel() < n:
+            raise ValueError("pass_count has fewer entries than mask rows")
+    if digest is not None:
+        _check_dtype(digest, "digest", np.uint64)
+        if digest.numel() < n:
+            raise ValueError("digest has fewer entries than mask rows")
+    _check(lib().grim_mask_summary(_ptr(mask), n, W, None if pass_count is None else _ptr(pass_count),
+                                   None if digest is None else _ptr(digest), _stream_handle(stream)))
 
 
 def grim_index_load(path: str, stream=None) -> Index:

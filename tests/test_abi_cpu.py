@@ -101,6 +101,14 @@ def test_scan_rejects_null_arguments():
     assert L.grim_seeds_build(ref, 16, 0, 15, None, ctypes.byref(h)) == grim.GRIM_EINVAL   # k = 15
     assert L.grim_seeds_build(None, 16, 0, 12, None, ctypes.byref(h)) == grim.GRIM_EINVAL
     L.grim_seeds_free(None)
+    # mask summaries: a NULL or misaligned mask, or a zero row width, fail before any device work
+    assert L.grim_mask_summary(None, 1, 4, None, None, None) == grim.GRIM_EINVAL
+    buf = ctypes.create_string_buffer(64)
+    base = ctypes.addressof(buf)
+    assert L.grim_mask_summary(base, 1, 0, None, None, None) == grim.GRIM_EINVAL
+    assert L.grim_mask_summary((base + 4) | 1, 1, 4, None, None, None) == grim.GRIM_EINVAL
+    assert L.grim_mask_summary(base, 1, 1 << 32, None, None, None) == grim.GRIM_EINVAL
+    assert L.grim_mask_summary(None, 0, 4, None, None, None) == grim.GRIM_OK   # nothing to do
     assert L.grim_index_info(None, None) == grim.GRIM_EINVAL
     assert L.grim_index_read(None, 1, 0, 0, None) == grim.GRIM_EINVAL
     L.grim_index_free(None)   # ignored

@@ -113,6 +113,17 @@ def test_reverse_complement():
     comp = bytes.maketrans(b"ACGTacgt", b"TGCAtgca")
     want = b"".join(s.translate(comp)[::-1] for s in seqs)
     assert got == want
+    # offsets past the end of the bases: that read is left alone, the call fails, the rest is written
+    bases = np.frombuffer(b"ACCGTTAGGA", np.uint8).copy()
+    offs = np.array([0, 4, 100, 10], np.int64)
+    out = empty((16,), torch.uint8)
+    out.fill_(ord("."))
+    with pytest.raises(grim.GrimError) as e:
+        grim.grim_reverse_complement(dev(bases), dev(offs), out)
+    assert e.value.code == grim.GRIM_EINVAL
+    torch.cuda.synchronize()
+    assert host(out)[:4].tobytes() == b"CGGT"
+    assert host(out)[4:10].tobytes() == b"......"
 
 
 def test_seed_errors():
