@@ -274,9 +274,12 @@ def main():
         "launch_shape": tuned,
     }
 
+    summ = None
+    if w.mode == "allbins":
+        out["mask_summary"], summ = summary_leg(mask, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, w, ref, rd, me, ep, idx, info, cand, mask if w.mode == "allbins"
-                                           else (cnt, pas))
+                                           else (cnt, pas), summ)
     if w.mode == "candidates" and not args.no_verify:
         out["verify"] = verify_leg(args, w, ref, rd, me, ep, reads, idx, cand, d_co, d_cb, pas, stream)
     if w.mode == "candidates" and not args.no_seeding:
@@ -525,7 +528,38 @@ def serving(args, ref, idx, info):
     return results
 
 
-def cpu_baseline(args, w, ref, rd, me, ep, idx, info, cand, gpu_out):
+def summary_leg(mask, stream):
+    """Per-read pass counts and digests of the whole last mask (outside the timed
+    steps): one pass over the mask in HBM, then the small copy a consumer makes."""
+    import torch
+    from paper_1708_04329_amd import grim
+    n, W = int(mask.shape[0]), int(mask.shape[1])
+    pc = torch.empty(n, dtype=torch.uint32, device="cuda")
+    dg = torch.empty(n, dtype=torch.uint64, device="cuda")
+    grim.grim_mask_summary(mask, pc, dg, stream)      # warm-up
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    grim.grim_mask_summary(mask, pc, dg, stream)
+    ev[1].record(stream)
+    h_pc = torch.empty(n, dtype=torch.int32, pin_memory=True)
+    h_dg = torch.empty(n, dtype=torch.int64, pin_memory=True)
+    ev[2].record(stream)
+    with torch.cuda.stream(stream):
+        h_pc.copy_(pc.view(torch.int32), non_blocking=True)
+        h_dg.copy_(dg.view(torch.int64), non_blocking=True)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    ms, d2h = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
+    mask_bytes = n * W * 4
+    log(f"mask summary: {mask_bytes / 1e9:.1f} GB of masks in {ms:.2f} ms ({mask_bytes / ms / 1e6:.0f} GB/s); "
+        f"copy of {n * 12 / 1e6:.1f} MB of summaries {d2h:.2f} ms")
+    res = {"kernel": "k_mask_summary", "ms": ms, "mask_bytes": mask_bytes, "GB_per_s": mask_bytes / ms / 1e6,
+           "frac_of_hbm_peak": mask_bytes / (ms * 1e-3) / HBM_PEAK, "d2h_ms": d2h, "d2h_bytes": n * 12,
+           "mean_pass_count": float(h_pc.numpy().view(np.uint32).mean())}
+    return res, (h_pc.numpy().view(np.uint32), h_dg.numpy().view(np.uint64))
+
+
+def cpu_baseline(args, w, ref, rd, me, ep, idx, info, cand, gpu_out, summ=None):
     """Time the CPU oracle on a bounded sample and check it against the GPU output."""
     import torch
     from oracle import Oracle
@@ -557,6 +591,10 @@ def cpu_baseline(args, w, ref, rd, me, ep, idx, info, cand, gpu_out):
         got = gpu_out.view(torch.int32)[torch.from_numpy(ids).cuda()].cpu().numpy().view(np.uint32)
         gp = np.unpackbits(got.view(np.uint8).reshape(len(ids), -1), axis=1, bitorder="little")[:, :nb]
         exact = bool(np.array_equal(gp, p))
+        if summ is not None:
+            # the sampled rows' pass counts and digests against the oracle's
+            want_c, want_d = o.mask_summary(p)
+            exact = exact and bool(np.array_equal(summ[0][ids], want_c) and np.array_equal(summ[1][ids], want_d))
         desc = f"{len(ids)} reads (seeded sample) x all {nb} bins"
     else:
         co, cb = cand

@@ -196,21 +196,27 @@ class Oracle:
         """Pass matrix [n, nb] -> uint32 words [n, ceil(nb/32)], bit x % 32 of word x // 32."""
         n, nb = passed.shape
         W = (nb + 31) // 32
-        words = np.zeros((n, W), dtype=np.uint64)
-        for x in range(nb):
-            words[:, x // 32] |= passed[:, x].astype(np.uint64) << np.uint64(x % 32)
-        return words.astype(np.uint32)
+        weights = np.uint64(1) << np.arange(32, dtype=np.uint64)      # bit b has weight 2^b
+        words = np.zeros((n, W), dtype=np.uint32)
+        step = max(1, (1 << 24) // max(1, W * 32))                     # rows per chunk
+        for r0 in range(0, n, step):
+            chunk = np.zeros((min(step, n - r0), W * 32), dtype=np.uint64)
+            chunk[:, :nb] = passed[r0:r0 + step]
+            words[r0:r0 + step] = (chunk.reshape(-1, W, 32) * weights).sum(axis=2).astype(np.uint32)
+        return words
 
     def mask_summary(self, passed: np.ndarray):
         """(pass count uint32 [n], digest uint64 [n]) of a pass matrix [n, nb]:
         the count of passing bins, and the sum over the packed row's words i of
         mix64((i << 32) | word_i), modulo 2^64."""
-        passed = np.asarray(passed).astype(bool)
+        passed = np.asarray(passed) != 0
         counts = passed.sum(axis=1).astype(np.uint32)
-        words = self.pack_rows(passed).astype(np.uint64)
+        words = self.pack_rows(passed)
         idx = np.arange(words.shape[1], dtype=np.uint64) << np.uint64(32)
+        digests = np.zeros(len(words), dtype=np.uint64)
         with np.errstate(over="ignore"):
-            digests = self.mix64(words | idx[None, :]).sum(axis=1, dtype=np.uint64)
+            for r in range(len(words)):
+                digests[r] = self.mix64(words[r].astype(np.uint64) | idx).sum(dtype=np.uint64)
         return counts, digests
 
     def scan_candidates(self, bits: np.ndarray, q: int, bases, offsets, cand_off, cand_bin,
