@@ -293,7 +293,8 @@ typedef struct {
   uint32_t lane_words;         /* all-bins: uint32 words = 32-bin groups per lane (4 or 8) */
   uint32_t cand_waves;         /* candidates: wavefronts per workgroup (0 = by vector size) */
   uint32_t cand_persistent;    /* candidates: 1 = fixed grid with reads handed out by an atomic
-                                  counter (uneven reads in one persistent launch) */
+                                  counter (uneven reads in one persistent launch); 2 = that grid
+                                  for calls of at least 2^20 reads, one wavefront per read below */
   uint32_t cand_groups_per_cu; /* candidates, persistent: workgroups per CU in the fixed grid */
   uint32_t cand_coop;          /* candidates, q >= 5: 1 = 4^q/512 lanes share a pair, each streaming
                                   64 contiguous bytes of the bin vector; 0 = one lane per pair */
@@ -303,7 +304,13 @@ typedef struct {
 } grim_tune_result;
 
 /* Time every launch shape of one mode on a sample read set and keep the
- * fastest on `idx` for later calls (and in the file named by the
+ * fastest on `idx` for later calls, unless it beats the default shape by less
+ * than 5% on the sample (then the default stays; short samples are dominated
+ * by launch overhead). The defaults: all-bins 1024 threads, 4096 reads per
+ * chunk, 4 words per lane; candidates 4 wavefronts per workgroup, cooperative
+ * lanes at q >= 5, and at q = 5 the persistent grid of 8 workgroups per CU
+ * for calls of 2^20 reads or more (cand_persistent = 2).
+ * The choice is also kept in the file named by the
  * GRIM_TUNE_CACHE environment variable, keyed by mode, q and size class, for
  * later processes). Mode: candidates if cand_off is non-NULL (device arrays
  * as in grim_filter_candidates), else all-bins. The sample should be large

@@ -130,7 +130,7 @@ int apply_result(grim_index* idx, const grim_tune_result* r) {
     idx->scan_tuned = true;
   } else if (r->mode == GRIM_MODE_CANDIDATES) {
     if (r->cand_waves > 8) return set_error(GRIM_EINVAL, "cand_waves must be in [0, 8]");
-    if (r->cand_persistent > 1) return set_error(GRIM_EINVAL, "cand_persistent must be 0 or 1");
+    if (r->cand_persistent > 2) return set_error(GRIM_EINVAL, "cand_persistent must be 0, 1 or 2");
     if (r->cand_groups_per_cu < 1 || r->cand_groups_per_cu > 64)
       return set_error(GRIM_EINVAL, "cand_groups_per_cu must be in [1, 64]");
     if (r->cand_coop > 1) return set_error(GRIM_EINVAL, "cand_coop must be 0 or 1");
@@ -258,6 +258,12 @@ extern "C" int grim_tune(grim_index* idx, const grim_reads* rd, const int64_t* c
             best.lane_words = (uint32_t)lw;
           }
         }
+    if (default_ms > 0 && best.best_ms > 0.95 * default_ms) {  // within noise of the default: keep it
+      best.best_ms = default_ms;
+      best.threads = 1024;
+      best.reads_per_chunk = 4096;
+      best.lane_words = 4;
+    }
     best.cand_waves = (uint32_t)idx->cand_cfg.waves;
     best.cand_persistent = (uint32_t)idx->cand_cfg.persistent;
     best.cand_groups_per_cu = (uint32_t)idx->cand_cfg.groups_per_cu;
@@ -301,7 +307,12 @@ extern "C" int grim_tune(grim_index* idx, const grim_reads* rd, const int64_t* c
             const double ms = time_it([&] { return launch_scan_candidates(a, c, s); });
             if (ms < 0) continue;
             ++tried;
-            if (coop == (idx->vec_words >= 32 ? dflt.coop : 0) && nw == 4 && !pers) default_ms = ms;
+            // the shape an untuned index uses (fill_geometry; at q = 5 the
+            // persistent grid 4 x 8 for calls of 2^20 reads or more)
+            const bool dpers = idx->vec_words == 32 && rd->n_reads >= kPersistentMinReads;
+            if (coop == (idx->vec_words >= 32 ? dflt.coop : 0) && nw == 4 && pers == (dpers ? 1 : 0) &&
+                gpc == (dpers ? 8 : 2))
+              default_ms = ms;
             if (ms < best.best_ms) {
               best.best_ms = ms;
               best.cand_waves = (uint32_t)nw;
@@ -310,6 +321,16 @@ extern "C" int grim_tune(grim_index* idx, const grim_reads* rd, const int64_t* c
               best.cand_coop = (uint32_t)coop;
             }
           }
+    // a shape that beats the default by under 5% on the sample is noise more
+    // often than not (short samples are dominated by launch overhead): keep the default
+    if (default_ms > 0 && best.best_ms > 0.95 * default_ms) {
+      const bool q5 = idx->vec_words == 32;
+      best.best_ms = default_ms;
+      best.cand_waves = 4;
+      best.cand_persistent = q5 ? 2u : 0u;
+      best.cand_groups_per_cu = q5 ? 8u : 2u;
+      best.cand_coop = idx->vec_words >= 32 ? (uint32_t)dflt.coop : 0u;
+    }
     best.threads = (uint32_t)idx->scan_cfg.threads;
     best.reads_per_chunk = (uint32_t)idx->scan_cfg.reads_per_chunk;
     best.lane_words = (uint32_t)idx->scan_cfg.lane_words;

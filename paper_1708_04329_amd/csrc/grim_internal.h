@@ -223,13 +223,16 @@ struct CandArgs {
   uint16_t* count_out;
   uint8_t* pass_out;
   uint32_t* status;
+  uint32_t grab;               // persistent mode: reads taken per counter increment (set at launch)
 };
 struct CandConfig {
   int waves = 0;         // wavefronts per workgroup (0: by vector size)
-  int persistent = 0;    // 1: fixed grid, reads handed out by an atomic counter
+  int persistent = 0;    // 1: fixed grid, reads handed out by an atomic counter;
+                         // 2: that grid for calls of at least kPersistentMinReads reads, else 0
   int groups_per_cu = 2; // persistent grid size = 256 CUs x groups_per_cu
   int coop = 1;          // 1: VW/16 lanes per pair (q >= 5), 0: one lane per pair
 };
+constexpr uint64_t kPersistentMinReads = 1ull << 20;
 hipError_t launch_scan_candidates(const CandArgs& a, const CandConfig& cfg, hipStream_t s);
 // Zero `n` uint32 words with a kernel (graph-safe, unlike a memset node).
 hipError_t launch_zero_words(uint32_t* p, uint32_t n, hipStream_t s);

@@ -20,9 +20,10 @@
 // moves.
 //
 // Two launch shapes: one wavefront per read (the hardware dispatcher
-// balances), or a persistent grid whose wavefronts take the next read from an
-// atomic counter until none are left (reads of uneven length and candidate
-// count in one launch, no per-workgroup dispatch cost).
+// balances), or a persistent grid whose wavefronts take the next reads from
+// an atomic counter until none are left (reads of uneven length and candidate
+// count in one launch, no per-wavefront dispatch cost, which bounds the
+// short-list case: 4M wavefronts of ~1.4 us each leave most of the chip idle).
 
 #include "grim_internal.h"
 
@@ -259,14 +260,14 @@ __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
     if (r < n_reads) one(r);
   } else {
     // every wavefront leaves once the counter has passed n_reads; reads are
-    // taken kGrab at a time so the counter sees few atomics
-    constexpr uint32_t kGrab = 8;
+    // taken a.grab at a time so the counter sees few atomics
+    const uint32_t grab = a.grab;
     while (true) {
       uint32_t r0 = 0;
-      if (lane == 0) r0 = atomicAdd(a.work, kGrab);
+      if (lane == 0) r0 = atomicAdd(a.work, grab);
       r0 = __shfl(r0, 0);
       if ((uint64_t)r0 >= n_reads) break;
-      const uint64_t r1 = min((uint64_t)r0 + kGrab, n_reads);
+      const uint64_t r1 = min((uint64_t)r0 + grab, n_reads);
       for (uint64_t r = r0; r < r1; ++r) one(r);
     }
   }
@@ -274,12 +275,20 @@ __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
 
 template <int VW, int NW, bool COOP>
 hipError_t launch_nw_layout(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
-  if (cfg.persistent) {
+  const bool persistent = cfg.persistent == 1 || (cfg.persistent == 2 && a.n_reads >= kPersistentMinReads);
+  if (persistent) {
     if (!a.work) return hipErrorInvalidValue;
     const uint64_t blocks = 256ull * (uint64_t)max(1, cfg.groups_per_cu);
+    // about 8192 pairs per counter increment (64 reads of the short 100 Mbp
+    // lists, ~49 pairs each; 8 of the 1024-pair uneven lists: measured best
+    // for each), but at least four increments per wavefront of the grid
+    CandArgs b = a;
+    const uint64_t per_read = std::max<uint64_t>(1, a.n_cand / std::max<uint64_t>(1, a.n_reads));
+    const uint64_t spread = a.n_reads / (4 * blocks * NW);
+    b.grab = (uint32_t)std::min<uint64_t>(64, std::max<uint64_t>(1, std::min(8192 / per_read, spread)));
     hipError_t e = launch_zero_words(a.work, 1, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_scan_cand<VW, NW, true, COOP>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, a);
+    hipLaunchKernelGGL((k_scan_cand<VW, NW, true, COOP>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, b);
   } else {
     const uint64_t blocks = (a.n_reads + NW - 1) / NW;
     if (blocks == 0) return hipSuccess;
