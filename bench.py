@@ -46,11 +46,11 @@ MEASURED_TRAFFIC = {
         "sha256": "36c0f7bd6ac64e188e003e149c5798eae28b2a41dbc1adc9d3d10d7a695846ee",
         "fetch_bytes": 82.3e9, "write_bytes": 224.8e9, "profile": "profiles/k_scan_allbins_c3_3.1Gbp_q5.md"},
     ("c4_candidates_uneven_3.1Gbp_q6", "scan_candidates.hip"): {
-        "sha256": "98d49adee9c76dbf24bd7655482e712a46cb6690a05e497f70334a4a718cb0dc",
+        "sha256": "7311515a8509d1f3793608222d0cb6ceee3238a0a440541c50746190fb4a6bba",
         "fetch_bytes": 1049.0e9, "write_bytes": 15.0e9, "profile": "profiles/k_scan_cand_c4_3.1Gbp_q6.md"},
     ("c2_candidates_100Mbp_q5", "scan_candidates.hip"): {
-        "sha256": "98d49adee9c76dbf24bd7655482e712a46cb6690a05e497f70334a4a718cb0dc",
-        "fetch_bytes": 14.2e9, "write_bytes": 0.6e9, "profile": "profiles/k_scan_cand_c2_100Mbp_q5.md"},
+        "sha256": "7311515a8509d1f3793608222d0cb6ceee3238a0a440541c50746190fb4a6bba",
+        "fetch_bytes": 15.2e9, "write_bytes": 1.1e9, "profile": "profiles/k_scan_cand_c2_100Mbp_q5.md"},
 }
 
 
