@@ -95,7 +95,8 @@ int grim_mask_summary(const uint32_t* mask, uint64_t n_reads, uint64_t mask_word
   if (!mask) return set_error(GRIM_EINVAL, "mask is NULL");
   if (mask_words == 0 || mask_words >= (1ull << 32)) return set_error(GRIM_EINVAL, "mask_words must be in [1, 2^32)");
   if (reinterpret_cast<uintptr_t>(mask) & 3u) return set_error(GRIM_EINVAL, "mask is not 4-byte aligned");
-  if (n_reads > (1ull << 40)) return set_error(GRIM_EINVAL, "too many reads");
+  if (n_reads > (1ull << 40) || mask_words > ((1ull << 60) / n_reads))
+    return set_error(GRIM_EINVAL, "mask larger than 2^62 bytes");
   if (!pass_count_out && !digest_out) return GRIM_OK;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const uint64_t blocks = n_reads < (1ull << 20) ? n_reads : (1ull << 20);
