@@ -315,6 +315,49 @@ def test_error_paths_leave_library_usable(oracle):
     assert np.array_equal(unpack_mask(m, nb), wp)
 
 
+def test_maximum_read_length(oracle):
+    """Reads of exactly 65535 tokens (the most a count can hold): a homopolymer, whose single
+    token reaches count 65535 (all 16 counter planes), and a random read; both in the all-bins
+    scan with uint16 counts and in candidate mode. One token more is rejected."""
+    import torch
+    rng = random.Random(65535)
+    q = 5
+    G, B, O = 30000, 64, 40
+    ref = bytearray(rand_ref(rng, G).tobytes())
+    ref[5000:5100] = b"A" * 100                   # an A run: bins around it hold token AAAAA
+    ref = np.frombuffer(bytes(ref), np.uint8).copy()
+    L = 65535 + q - 1
+    seqs = [b"A" * L, bytes(rng.choice(b"ACGT") for _ in range(L))]
+    rd = synth.reads_from_strings(seqs)
+    idx = build(ref, B, O, q)
+    nb = idx.info()["n_bins"]
+    E = np.array([0, 9000], np.uint16)
+    log("maximum read length: tokens", L - q + 1, "bins", nb)
+    m, c = gpu_scan(idx, rd, counts_dtype=torch.uint16, max_edits=E, allow_short_overlap=True)
+    bits = oracle.bits(ref, B, O, q)
+    want_c, want_p = oracle.scan_all(bits, q, rd.bases, rd.offsets, max_edits=E)
+    assert np.array_equal(c.astype(np.uint16), want_c) and np.array_equal(unpack_mask(m, nb), want_p)
+    assert want_c[0].max() == 65535 and want_p[0].any() and not want_p[0].all()
+    # candidate mode: every bin of both reads
+    co = np.array([0, nb, 2 * nb], np.int64)
+    cb = np.concatenate([np.arange(nb, dtype=np.int32)] * 2)
+    cnt = empty((2 * nb,), torch.uint16)
+    pas = empty((2 * nb,), torch.uint8)
+    rs = grim.ReadSet(dev(rd.bases), dev(rd.offsets), max_edits=dev(E), allow_short_overlap=True)
+    grim.grim_filter_candidates(idx, rs, dev(co), dev(cb), cnt, pas)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(cnt.view(torch.int16)).view(np.uint16), want_c.reshape(-1))
+    assert np.array_equal(host(pas), want_p.reshape(-1))
+    # 65536 tokens: rejected, and the index stays usable
+    rd2 = synth.reads_from_strings([b"A" * (L + 1)])
+    mask = empty((1, idx.info()["mask_words"]), torch.uint32)
+    with pytest.raises(grim.GrimError) as e:
+        grim.grim_filter_scan(idx, grim.ReadSet(dev(rd2.bases), dev(rd2.offsets), allow_short_overlap=True), mask)
+    assert e.value.code == grim.GRIM_EINVAL
+    m2, _ = gpu_scan(idx, rd, max_edits=E, allow_short_overlap=True)
+    assert np.array_equal(unpack_mask(m2, nb), want_p)
+
+
 def test_save_load_roundtrip(tmp_path):
     import torch
     rng = random.Random(6)
