@@ -99,8 +99,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(bins or reads would shard across GPUs without any collective; see the design notes)",
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(bin ranges or reads would shard across GPUs with no collective on the filter's path)",
               file=sys.stderr)
         sys.exit(2)
 
