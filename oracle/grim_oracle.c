@@ -32,8 +32,8 @@
  *     the reference there with dynamic programming; a passing location that
  *     yields no mapping within the error budget counts against the filter.
  *
- * Conventions the paper leaves open (each one is listed with its reading in
- * the design notes; the GPU path implements the same reading independently):
+ * Conventions the paper leaves open, with the reading taken here (the GPU
+ * path implements the same readings independently):
  *   - bins are B bases wide; bin x is extended by O bases into the next bin:
  *     token starts s with x*B <= s < min(x*B + B + O, G - q + 1) count for bin x;
  *     the number of bins is ceil(G / B); the last bin is partial;

@@ -2,7 +2,7 @@
 
 A workload bundles a genome recipe, a read recipe and the filter parameters
 (bin size B, overlap O, token length q, error budget). Choices the workload
-descriptions leave open are made here and listed in the design notes:
+descriptions leave open are made here:
 B = 2048 everywhere; O = L_max + E_max (105 for 100 bp reads at E=5; 263 for
 the 3.1 Gbp index, enough for 250 bp reads at 5%); the human-scale repeat
 families are 64 consensus sequences of 300 bp and 64 of 6 kbp; reads use
