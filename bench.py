@@ -342,12 +342,40 @@ def verify_leg(args, w, ref, rd, me, ep, reads, idx, cand, d_co, d_cb, pas, stre
     hi = torch.clamp(x * w.bin_size + w.bin_size + w.overlap, max=last)
     text = torch.where(hi > x * w.bin_size, hi + w.q - 1 - x * w.bin_size, torch.zeros_like(hi))
     cells = int((lens[rid[sel]].to(torch.int64) * text).sum().item())
-    del rid, sel, x, hi, text
+    del x, hi, text
     log(f"verify: {n_pass:,} passing pairs aligned in {align_ms:.2f} ms ({cells / (align_ms * 1e-3) / 1e9:.0f} "
         f"GCUPS); {n_map:,} map; paper false-negative rate {1 - n_map / max(1, n_pass):.4f}")
     res = {"pairs_aligned": n_pass, "mapping": n_map, "paper_false_negative_rate": 1 - n_map / max(1, n_pass),
            "align_kernel_ms": align_ms, "call_ms": elapsed * 1e3, "dp_cells": cells,
            "gcups": cells / (align_ms * 1e-3) / 1e9, "text_bases_per_bin": span}
+    # the bounded form: distances above E_r reported as E_r + 1, the same match flags
+    dist_b = torch.empty_like(dist)
+    match_b = torch.empty_like(match)
+    grim.grim_verify_candidates_bounded(idx, reads, d_co, d_cb, pas, dist_b, match_b, stream)
+    torch.cuda.synchronize()
+    grim.grim_profile_enable(True)
+    grim.grim_profile_read(reset=True)
+    for _ in range(args.steps):
+        grim.grim_verify_candidates_bounded(idx, reads, d_co, d_cb, pas, dist_b, match_b, stream)
+    torch.cuda.synchronize()
+    kb = grim.grim_profile_read(reset=True)["verify"]
+    grim.grim_profile_enable(False)
+    bounded_ms = kb["total_ms"] / max(1, kb["launches"])
+    if me is not None:
+        E_read = torch.from_numpy(me.astype(np.int64)).cuda()
+    else:
+        e = ep.astype(np.int64) if ep is not None else np.full(rd.n, 0, np.int64)
+        E_read = torch.from_numpy((rd.lengths.astype(np.int64) * e + 999) // 1000).cuda()
+    E_pair = E_read[rid[sel]]
+    d_x = dist[:P].view(torch.int16)[sel].to(torch.int64) & 0xFFFF
+    d_b = dist_b[:P].view(torch.int16)[sel].to(torch.int64) & 0xFFFF
+    consistent = bool(torch.equal(d_b, torch.minimum(d_x, E_pair + 1)) and torch.equal(match_b[:P], match[:P]))
+    del rid, sel, E_pair, d_x, d_b, dist_b, match_b
+    log(f"verify bounded by E: {bounded_ms:.2f} ms ({align_ms / bounded_ms:.2f}x the exact form); "
+        f"equal to min(exact, E + 1) with the same matches: {consistent}")
+    res["bounded"] = {"align_kernel_ms": bounded_ms, "speedup_vs_exact": align_ms / bounded_ms,
+                      "equivalent_cells_per_s": cells / (bounded_ms * 1e-3),
+                      "equal_to_min_exact_E_plus_1": consistent}
     if not args.no_cpu_baseline:
         from oracle import Oracle
         o = Oracle()

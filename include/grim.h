@@ -247,6 +247,19 @@ void grim_seeds_free(grim_seeds* seeds);
 int grim_seed_candidates(const grim_seeds* seeds, const grim_reads* reads, uint32_t bin_size, uint32_t cap,
                          int64_t* cand_off, int32_t* cand_bin, uint64_t* n_cand_out, void* hip_stream);
 
+/* grim_verify_candidates with distances bounded by each read's error budget:
+ * dist_out[k] is the same smallest edit distance when it is <= E_r and
+ * E_r + 1 (at most 0xFFFE) when it is larger; match_out[k] is unchanged
+ * (dist <= E_r). A mapper's verification only needs to know whether a
+ * location maps within E_r (Section 1, seed-and-extend step 5), and the
+ * bound lets each lane advance only the 32-row words of the dynamic program
+ * that can still hold a distance <= E_r (Myers 1999, Section 4: the block
+ * form with Ukkonen's cutoff), which at most locations is the first one.
+ * Arguments, requirements and errors as for grim_verify_candidates. */
+int grim_verify_candidates_bounded(const grim_index* idx, const grim_reads* reads, const int64_t* cand_off,
+                                   const int32_t* cand_bin, uint64_t n_cand, const uint8_t* verify_mask,
+                                   uint16_t* dist_out, uint8_t* match_out, void* hip_stream);
+
 /* Per-read summary of pass masks, for a consumer that keeps the masks in
  * device memory and copies back only a few bytes per read (a read's row is
  * 189 KB at human scale; the masks are the filter's output, Section 3 steps

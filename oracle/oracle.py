@@ -13,7 +13,7 @@ follows (arXiv 1708.04329):
   * scan_candidates    Section 3, steps 4-5 (bin of the location's first base)
   * seed_candidates    Section 1, seed-and-extend steps 2-4 (seeds of a read,
                        looked up in the reference, give candidate locations)
-  * semiglobal_distance, verify
+  * semiglobal_distance, verify, verify_bounded
                        Section 1, seed-and-extend step 5 (dynamic-programming
                        alignment of the read at a location) and Section 5,
                        evaluation metrics (a passing location either yields a
@@ -269,6 +269,28 @@ class Oracle:
                                     err_permille, _p(co), _p(cb), _p(vm), _p(dist), _p(match), self.threads)
         if rc != 0:
             raise ValueError("candidate bin out of range")
+        return dist, match
+
+    def verify_bounded(self, ref, B: int, O: int, q: int, bases, offsets, cand_off, cand_bin, verify_mask=None,
+                       max_edits=None, err_pm_per_read=None, err_permille: int = 0):
+        """verify() with each distance above the read's budget E_r reported as E_r + 1
+        (capped at 0xFFFE); match flags and skipped pairs (0xFFFF) unchanged."""
+        dist, match = self.verify(ref, B, O, q, bases, offsets, cand_off, cand_bin, verify_mask, max_edits,
+                                  err_pm_per_read, err_permille)
+        offs = np.ascontiguousarray(offsets, np.int64)
+        co = np.ascontiguousarray(cand_off, np.int64)
+        n = len(offs) - 1
+        for r in range(n):
+            L = int(offs[r + 1] - offs[r])
+            if max_edits is not None:
+                E = int(max_edits[r])
+            else:
+                e = int(err_pm_per_read[r]) if err_pm_per_read is not None else int(err_permille)
+                E = self.max_edits(L, e)
+            seg = slice(int(co[r]), int(co[r + 1]))
+            d = dist[seg]
+            over = (d != 0xFFFF) & (d.astype(np.int64) > E)
+            d[over] = min(E + 1, 0xFFFE)
         return dist, match
 
     def seed_candidates(self, ref, bases, offsets, k: int, B: int, cap: int):

@@ -658,10 +658,13 @@ int grim_filter_candidates(const grim_index* cidx, const grim_reads* rd, const i
   return rc;
 }
 
-int grim_verify_candidates(const grim_index* cidx, const grim_reads* rd, const int64_t* cand_off,
-                           const int32_t* cand_bin, uint64_t n_cand, const uint8_t* verify_mask, uint16_t* dist_out,
-                           uint8_t* match_out, void* hip_stream) {
-  clear_error();
+}  // extern "C"
+
+namespace {
+
+int verify_impl(const grim_index* cidx, const grim_reads* rd, const int64_t* cand_off, const int32_t* cand_bin,
+                uint64_t n_cand, const uint8_t* verify_mask, uint16_t* dist_out, uint8_t* match_out,
+                void* hip_stream, bool bounded) {
   int rc = check_reads_args(cidx, rd);
   if (rc) return rc;
   grim_index* idx = const_cast<grim_index*>(cidx);
@@ -709,6 +712,7 @@ int grim_verify_candidates(const grim_index* cidx, const grim_reads* rd, const i
   a.bucket = ws.vbucket;
   a.read_sel = ws.vread_sel;
   a.chunk_sum = ws.vchunk_sum;
+  a.bounded = bounded ? 1u : 0u;
   GRIM_HIP_TRY(launch_verify_count(a, s));
   // pairs per length class, and the status of the inputs
   uint64_t* counts = ws.vbucket_host;
@@ -737,6 +741,24 @@ int grim_verify_candidates(const grim_index* cidx, const grim_reads* rd, const i
   rc = finish_status(idx, s);
   pv.collect();
   return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int grim_verify_candidates(const grim_index* cidx, const grim_reads* rd, const int64_t* cand_off,
+                           const int32_t* cand_bin, uint64_t n_cand, const uint8_t* verify_mask, uint16_t* dist_out,
+                           uint8_t* match_out, void* hip_stream) {
+  clear_error();
+  return verify_impl(cidx, rd, cand_off, cand_bin, n_cand, verify_mask, dist_out, match_out, hip_stream, false);
+}
+
+int grim_verify_candidates_bounded(const grim_index* cidx, const grim_reads* rd, const int64_t* cand_off,
+                                   const int32_t* cand_bin, uint64_t n_cand, const uint8_t* verify_mask,
+                                   uint16_t* dist_out, uint8_t* match_out, void* hip_stream) {
+  clear_error();
+  return verify_impl(cidx, rd, cand_off, cand_bin, n_cand, verify_mask, dist_out, match_out, hip_stream, true);
 }
 
 }  // extern "C"

@@ -142,6 +142,7 @@ struct VerifyArgs {
   uint64_t* chunk_sum;       // [chunks][kVerifyBuckets] pair counts, then first slots
   uint64_t* item_pair;       // work list: pair index
   uint32_t* item_read;       //            and its read
+  uint32_t bounded;          // 1: distances above E_r reported as E_r + 1 (Ukkonen's cutoff)
 };
 // Chunks of reads of the list passes.
 uint64_t verify_chunks(uint64_t n_reads);

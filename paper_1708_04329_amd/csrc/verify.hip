@@ -27,6 +27,8 @@
 // counters); a second pass lists the pairs class by class, so that one
 // launch per class runs lanes with equal word counts in lock step.
 
+#include <type_traits>
+
 #include "grim_internal.h"
 
 namespace grim {
@@ -251,7 +253,73 @@ struct Column {
   }
 };
 
+// Bounded form of the same step (Myers 1999, Section 4: the block-based
+// algorithm with Ukkonen's cutoff): only words 0..y advance, y being the last
+// word that can hold a distance <= k in this column; every cell below it is
+// known to exceed k. sc[w] is the distance at word w's last row (row `top`
+// for word W - 1). Word y + 1 joins when its first row can reach k: the last
+// active word's bottom was <= k in the previous column and either the text
+// base matches that first row or the bottom decreased. It joins as if its
+// previous column rose by one per row (Myers' initialisation; cells whose
+// true distance is <= k still come out exact). A last active word leaves once
+// its last row's distance minus its +1 bits exceeds k (no cell of it can then
+// be <= k). Distances <= k are exact; larger ones are reported as k + 1.
 template <int W>
+struct ColumnB {
+  uint32_t r0[W], r1[W], va[W];
+  uint32_t pv[W], mv[W];
+  int32_t sc[W];
+  uint32_t top, lastmask;  // lastmask: rows 0..top of word W - 1
+  int32_t k, y, best;
+
+  template <bool CHECKED>
+  __device__ __forceinline__ void step(uint32_t c) {
+    const uint32_t c0 = 0u - (c & 1u), c1 = 0u - ((c >> 1) & 1u);
+    const uint32_t valid = (!CHECKED || c < 4u) ? 0xFFFFFFFFu : 0u;
+    uint32_t php = 0, mhp = 0;
+    int32_t hprev = 0;  // horizontal difference out of the previous word's last row
+    int32_t yn = y;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      uint32_t eq = __builtin_amdgcn_bitop3_b32(va[w], r0[w], c0, 0x90);
+      eq = __builtin_amdgcn_bitop3_b32(eq, r1[w], c1, 0x90);
+      if (CHECKED) eq &= valid;
+      if (w > 0 && w == yn + 1 && sc[w - 1] - hprev <= k && ((eq & 1u) || hprev < 0)) {
+        pv[w] = 0xFFFFFFFFu;
+        mv[w] = 0;
+        sc[w] = sc[w - 1] - hprev + (w == W - 1 ? (int32_t)top + 1 : 32);
+        yn = w;
+      }
+      if (w <= yn) {
+        const uint32_t xv = eq | mv[w];
+        eq |= mhp >> 31;
+        const uint32_t sum = (eq & pv[w]) + pv[w];
+        const uint32_t xh = __builtin_amdgcn_bitop3_b32(sum, pv[w], eq, 0xBE);  // (sum ^ pv) | eq
+        const uint32_t ph = mv[w] | ~(xh | pv[w]);
+        const uint32_t mh = pv[w] & xh;
+        const uint32_t bit = w == W - 1 ? top : 31u;
+        hprev = (int32_t)((ph >> bit) & 1u) - (int32_t)((mh >> bit) & 1u);
+        sc[w] += hprev;
+        const uint32_t phs = __builtin_amdgcn_alignbit(ph, php, 31);
+        const uint32_t mhs = __builtin_amdgcn_alignbit(mh, mhp, 31);
+        pv[w] = mhs | ~(xv | phs);
+        mv[w] = phs & xv;
+        php = ph;
+        mhp = mh;
+      }
+    }
+    y = yn;
+    if (y == W - 1) best = min(best, sc[W - 1]);
+    // going up from a word's last row the distance falls by at most one per
+    // +1 bit, so a last active word whose last row minus its +1 bits exceeds
+    // k holds no cell <= k and leaves
+#pragma unroll
+    for (int w = W - 1; w >= 1; --w)
+      if (y == w && sc[w] - (int32_t)__popc(w == W - 1 ? pv[w] & lastmask : pv[w]) > k) y = w - 1;
+  }
+};
+
+template <int W, bool BOUNDED>
 __global__ __launch_bounds__(256) void k_verify_align(VerifyArgs a, uint64_t first, uint64_t count) {
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
@@ -268,7 +336,11 @@ __global__ __launch_bounds__(256) void k_verify_align(VerifyArgs a, uint64_t fir
   if (lo > hi) lo = hi;
   hi = hi > lo ? hi + a.q - 1 : lo;
 
-  Column<W> col;
+  // the read's error budget, recovered from its threshold
+  const int32_t T = a.thr[r];
+  const int64_t E = ((int64_t)L - (int64_t)a.q + 1 - (int64_t)T) / (int64_t)a.q;
+  using Col = typename std::conditional<BOUNDED, ColumnB<W>, Column<W>>::type;
+  Col col;
   const uint8_t* rd = a.bases + o0;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
@@ -290,8 +362,18 @@ __global__ __launch_bounds__(256) void k_verify_align(VerifyArgs a, uint64_t fir
     col.mv[w] = 0;
   }
   col.top = (L - 1) & 31u;
-  col.score = (int32_t)L;
   col.best = (int32_t)L;
+  if constexpr (BOUNDED) {
+    // column 0: row i holds distance i + 1, so the words up to the one holding
+    // row k - 1 start active (word 0 always)
+    col.k = (int32_t)min<int64_t>(E, 1 << 20);
+    col.lastmask = col.top == 31u ? 0xFFFFFFFFu : (2u << col.top) - 1u;
+    col.y = col.k >= 1 ? min((int32_t)W - 1, (col.k - 1) / 32) : 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) col.sc[w] = w == W - 1 ? (int32_t)L : 32 * (w + 1);
+  } else {
+    col.score = (int32_t)L;
+  }
 
   const uint8_t* txt = a.ref;
   uint64_t j = lo;
@@ -314,9 +396,8 @@ __global__ __launch_bounds__(256) void k_verify_align(VerifyArgs a, uint64_t fir
   }
   for (; j < hi; ++j) col.template step<true>(txt[j]);
 
-  const int32_t T = a.thr[r];
-  const int64_t E = ((int64_t)L - (int64_t)a.q + 1 - (int64_t)T) / (int64_t)a.q;
-  const uint32_t d = (uint32_t)min(col.best, (int32_t)0xFFFE);
+  uint32_t d = (uint32_t)min(col.best, (int32_t)0xFFFE);
+  if constexpr (BOUNDED) d = (int64_t)col.best <= (int64_t)col.k ? (uint32_t)col.best : (uint32_t)min<int64_t>((int64_t)col.k + 1, 0xFFFE);
   a.dist_out[k] = (uint16_t)d;
   a.match_out[k] = (int64_t)d <= E ? 1 : 0;
 }
@@ -325,7 +406,8 @@ template <int W>
 hipError_t launch_align_w(const VerifyArgs& a, uint64_t first, uint64_t count, hipStream_t s) {
   const uint64_t blocks = (count + 255) / 256;
   if (blocks > 0x7FFFFFFFull) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(k_verify_align<W>, dim3((unsigned)blocks), dim3(256), 0, s, a, first, count);
+  if (a.bounded) hipLaunchKernelGGL((k_verify_align<W, true>), dim3((unsigned)blocks), dim3(256), 0, s, a, first, count);
+  else hipLaunchKernelGGL((k_verify_align<W, false>), dim3((unsigned)blocks), dim3(256), 0, s, a, first, count);
   return hipGetLastError();
 }
 

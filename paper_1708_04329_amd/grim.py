@@ -139,7 +139,7 @@ EXPORTS = ["grim_abi_version", "grim_last_error", "grim_build_index", "grim_inde
            "grim_serve_submit", "grim_serve_poll", "grim_serve_wait", "grim_serve_release", "grim_serve_cancel",
            "grim_serve_stats", "grim_serve_reset_stats", "grim_serve_destroy", "grim_verify_candidates",
            "grim_seeds_build", "grim_seeds_info", "grim_seeds_free", "grim_seed_candidates",
-           "grim_reverse_complement", "grim_mask_summary"]
+           "grim_reverse_complement", "grim_mask_summary", "grim_verify_candidates_bounded"]
 
 _lib = None
 
@@ -166,6 +166,7 @@ def lib(path: str = LIB_PATH):
         "grim_filter_scan": ([P, ctypes.POINTER(_Reads), P, P, U32, P], I),
         "grim_filter_candidates": ([P, ctypes.POINTER(_Reads), P, P, U64, P, P, P], I),
         "grim_verify_candidates": ([P, ctypes.POINTER(_Reads), P, P, U64, P, P, P, P], I),
+        "grim_verify_candidates_bounded": ([P, ctypes.POINTER(_Reads), P, P, U64, P, P, P, P], I),
         "grim_seeds_build": ([P, U64, U32, U32, P, PP], I),
         "grim_seeds_info": ([P, ctypes.POINTER(SeedsInfo)], I),
         "grim_seeds_free": ([P], None),
@@ -475,6 +476,20 @@ def grim_verify_candidates(index: Index, reads: ReadSet, cand_off, cand_bin, ver
     _check(lib().grim_verify_candidates(index.handle, ctypes.byref(r), _ptr(cand_off), _ptr(cand_bin),
                                         len(cand_bin), _ptr(verify_mask), _ptr(dist_out), _ptr(match_out),
                                         _stream_handle(stream)))
+
+
+def grim_verify_candidates_bounded(index: Index, reads: ReadSet, cand_off, cand_bin, verify_mask=None,
+                                   dist_out=None, match_out=None, stream=None):
+    """As grim_verify_candidates, with distances above E_r reported as E_r + 1 (faster)."""
+    _check_dtype(cand_off, "cand_off", np.int64)
+    _check_dtype(cand_bin, "cand_bin", np.int32)
+    _check_dtype(verify_mask, "verify_mask", np.uint8)
+    _check_dtype(dist_out, "dist_out", np.uint16)
+    _check_dtype(match_out, "match_out", np.uint8)
+    r = reads._struct()
+    _check(lib().grim_verify_candidates_bounded(index.handle, ctypes.byref(r), _ptr(cand_off), _ptr(cand_bin),
+                                                len(cand_bin), _ptr(verify_mask), _ptr(dist_out),
+                                                _ptr(match_out), _stream_handle(stream)))
 
 
 def grim_profile_enable(on: bool = True):

@@ -125,7 +125,7 @@ def main(argv=None):
         for e in range(e_max + 1):
             rs = grim.ReadSet(d_bases, d_offs, err_permille_all=10 * e)
             grim.grim_filter_candidates(idx, rs, co, cbv[:P], cnt, pas)
-            grim.grim_verify_candidates(idx, rs, co, cbv[:P], None, dist, match)   # every candidate
+            grim.grim_verify_candidates_bounded(idx, rs, co, cbv[:P], None, dist, match)   # every candidate
             torch.cuda.synchronize()
             pv, mv = pas[:P].to(torch.int64), match[:P].to(torch.int64)
             n_pass = int(pv.sum().item())

@@ -44,7 +44,7 @@ def mutate(rng: random.Random, s: bytes, k: int) -> bytes:
     return bytes(b)
 
 
-def run_verify(idx, rd, co, cb, mask=None, **edits):
+def run_verify(idx, rd, co, cb, mask=None, bounded=False, **edits):
     import torch
     P = max(1, len(cb))
     dist = empty((P,), torch.uint16)
@@ -52,7 +52,8 @@ def run_verify(idx, rd, co, cb, mask=None, **edits):
     me, ep = edits.get("max_edits"), edits.get("err_permille")
     rs = grim.ReadSet(dev(rd.bases), dev(rd.offsets), max_edits=None if me is None else dev(me),
                       err_permille=None if ep is None else dev(ep), allow_short_overlap=True)
-    grim.grim_verify_candidates(idx, rs, dev(co), dev(cb), None if mask is None else dev(mask), dist, match)
+    fn = grim.grim_verify_candidates_bounded if bounded else grim.grim_verify_candidates
+    fn(idx, rs, dev(co), dev(cb), None if mask is None else dev(mask), dist, match)
     torch.cuda.synchronize()
     return host(dist.view(torch.int16)).view(np.uint16)[:len(cb)], host(match)[:len(cb)]
 
@@ -91,12 +92,54 @@ def test_verify_matches_oracle_random(oracle, seed):
     assert len(bad) == 0, [(int(k), int(got_d[k]), int(want_d[k])) for k in bad[:8]]
     assert np.array_equal(got_m, want_m)
     assert want_m.any() and not want_m.all()
+    # bounded: exact up to E_r, E_r + 1 above it, the same match flags
+    bd, bm = run_verify(idx, rd, co, cb, bounded=True, max_edits=E)
+    wbd, wbm = oracle.verify_bounded(ref, B, O, q, rd.bases, rd.offsets, co, cb, max_edits=E)
+    bad = np.nonzero(bd != wbd)[0]
+    assert len(bad) == 0, [(int(k), int(bd[k]), int(wbd[k]), int(want_d[k])) for k in bad[:8]]
+    assert np.array_equal(bm, want_m)
+    rid = np.repeat(np.arange(rd.n), np.diff(co))
+    assert (bd[want_d <= E[rid]] == want_d[want_d <= E[rid]]).all()
+    assert ((bd > E[rid]) == (want_d > E[rid])).all()
     # a mask selects pairs; the rest read 0xFFFF / 0
     mask = np.array([rng.random() < 0.5 for _ in range(len(cb))], np.uint8)
     got_d, got_m = run_verify(idx, rd, co, cb, mask=mask, max_edits=E)
     want_d, want_m = oracle.verify(ref, B, O, q, rd.bases, rd.offsets, co, cb, verify_mask=mask, max_edits=E)
     assert np.array_equal(got_d, want_d) and np.array_equal(got_m, want_m)
     assert (got_d[mask == 0] == 0xFFFF).all()
+    bd, bm = run_verify(idx, rd, co, cb, mask=mask, bounded=True, max_edits=E)
+    wbd, _ = oracle.verify_bounded(ref, B, O, q, rd.bases, rd.offsets, co, cb, verify_mask=mask, max_edits=E)
+    assert np.array_equal(bd, wbd) and np.array_equal(bm, want_m)
+
+
+@pytest.mark.parametrize("E_all", [0, 1, 31, 32, 33, 70])
+def test_verify_bounded_budgets(oracle, E_all):
+    """The bounded form at budgets that put the cutoff inside the first word, on a word edge and
+    beyond it, on reads of 40..300 bases with a few edits: exact up to E, E + 1 above."""
+    rng = random.Random(900 + E_all)
+    G, B, O, q = 60_000, 500, 320, 5
+    ref = rand_ref(rng, G)
+    seqs, truth = [], []
+    for i in range(120):
+        L = rng.choice([40, 64, 65, 100, 150, 200, 257, 300])
+        p = rng.randrange(0, G - L)
+        seqs.append(mutate(rng, ref[p:p + L].tobytes(), rng.randrange(0, 40)))
+        truth.append(p // B)
+    seqs = [s if len(s) >= q else s + b"ACGTA" for s in seqs]
+    rd = synth.reads_from_strings(seqs)
+    nb = -(-G // B)
+    cand = [sorted({truth[r], max(0, truth[r] - 1), rng.randrange(nb)}) for r in range(rd.n)]
+    co = np.zeros(rd.n + 1, np.int64)
+    co[1:] = np.cumsum([len(c) for c in cand])
+    cb = np.concatenate([np.array(c, np.int32) for c in cand])
+    idx = grim.grim_build_index(dev(ref), B, O, q, grim.LAYOUT_REF)
+    E = np.full(rd.n, E_all, np.uint16)
+    bd, bm = run_verify(idx, rd, co, cb, bounded=True, max_edits=E)
+    wbd, wbm = oracle.verify_bounded(ref, B, O, q, rd.bases, rd.offsets, co, cb, max_edits=E)
+    bad = np.nonzero(bd != wbd)[0]
+    assert len(bad) == 0, [(int(k), int(bd[k]), int(wbd[k])) for k in bad[:8]]
+    assert np.array_equal(bm, wbm)
+    log("bounded E", E_all, "pairs", len(cb), "mapping", int(wbm.sum()))
 
 
 def test_verify_short_reference_and_edges(oracle):
@@ -114,6 +157,9 @@ def test_verify_short_reference_and_edges(oracle):
         E = np.full(rd.n, 3, np.uint16)
         got = run_verify(idx, rd, co, cb, max_edits=E)
         want = oracle.verify(ref, B, O, q, rd.bases, rd.offsets, co, cb, max_edits=E)
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), (G, B, O, q)
+        got = run_verify(idx, rd, co, cb, bounded=True, max_edits=E)
+        want = oracle.verify_bounded(ref, B, O, q, rd.bases, rd.offsets, co, cb, max_edits=E)
         assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), (G, B, O, q)
 
 
@@ -143,6 +189,12 @@ def test_verify_passing_candidates_uneven_recipe(oracle):
     want_d, want_m = oracle.verify(ref, w.bin_size, w.overlap, w.q, rd.bases, rd.offsets, co, cb, verify_mask=p,
                                    err_pm_per_read=ep)
     assert np.array_equal(got_d, want_d) and np.array_equal(got_m, want_m)
+    grim.grim_verify_candidates_bounded(idx, rs, d_co, d_cb, pas, dist, match)
+    torch.cuda.synchronize()
+    wbd, _ = oracle.verify_bounded(ref, w.bin_size, w.overlap, w.q, rd.bases, rd.offsets, co, cb, verify_mask=p,
+                                   err_pm_per_read=ep)
+    assert np.array_equal(host(dist.view(torch.int16)).view(np.uint16), wbd)
+    assert np.array_equal(host(match), want_m)
     rid = np.repeat(np.arange(rd.n), np.diff(co))
     truth = cb == (rd.truth_pos // w.bin_size)[rid]
     assert truth.sum() > rd.n // 2
