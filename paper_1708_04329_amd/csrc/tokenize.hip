@@ -13,10 +13,10 @@
 //
 // A wavefront tokenises eight reads at once: lane j < 8 validates read j and
 // writes its threshold, then the 64 lanes walk the reads' padded token ranges
-// as one flat range, four consecutive tokens per lane and step. Each lane
-// loads the q + 3 bases its four tokens span, slides a 2q-bit window over
-// them and writes the four entries with one 16-byte store. A read's range is
-// a multiple of 32 tokens, so a group of four never straddles two reads, and
+// as one flat range, eight consecutive tokens per lane and group. Each lane
+// loads the q + 7 bases its eight tokens span, slides a 2q-bit window over
+// them and writes the entries with two 16-byte stores. A read's range is a
+// multiple of 32 tokens, so a group of eight never straddles two reads, and
 // every base load lies inside the read (positions past its end count as
 // non-ACGT without a load).
 
@@ -100,17 +100,19 @@ __global__ __launch_bounds__(256) void k_tokenize(TokArgs a) {
   const uint32_t total = start[kTokReads];
   constexpr uint32_t R4 = 1u << (2 * Q);
   constexpr uint32_t MASK = R4 - 1u;
-  constexpr int NB = Q + 3;  // bases spanned by four consecutive tokens
+  constexpr int TPG = 8;            // consecutive tokens per lane and group
+  constexpr int NB = Q + TPG - 1;   // bases they span
+  constexpr uint32_t kSpan = 64u * TPG;
   const uint32_t sh = a.tok_shift;
 
-  for (uint32_t f0 = 4u * lane; f0 < total; f0 += 512u) {
-    // two groups of four tokens per lane and step, their loads issued together
+  for (uint32_t f0 = TPG * lane; f0 < total; f0 += 2u * kSpan) {
+    // two groups per lane and step, their loads issued together
     uint32_t by[2][NB];
     uint32_t i[2], n[2];
     uint32_t* out[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const uint32_t f = f0 + 256u * h;
+      const uint32_t f = f0 + kSpan * h;
       const uint8_t* s = src[0];
       uint32_t* d = dst[0];
       uint32_t nt = ntok[0], st = 0;
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(256) void k_tokenize(TokArgs a) {
       i[h] = f - st;
       n[h] = live ? nt : 0u;
       out[h] = d + i[h];
-      // bases i .. i + Q + 2; positions at or past the read's end (L = nt + Q - 1)
+      // bases i .. i + NB - 1; positions at or past the read's end (L = nt + Q - 1)
       // are not loaded, nor is anything for a group past the flat range
       const uint32_t lim = live ? nt + (Q - 1) : 0u;
 #pragma unroll
@@ -129,8 +131,8 @@ __global__ __launch_bounds__(256) void k_tokenize(TokArgs a) {
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      if (f0 + 256u * h >= total) continue;
-      uint32_t code = 0, v[4];
+      if (f0 + kSpan * h >= total) continue;
+      uint32_t code = 0, v[TPG];
       int last_bad = -1;  // position of the latest non-ACGT base
 #pragma unroll
       for (int m = 0; m < NB; ++m) {
@@ -142,7 +144,10 @@ __global__ __launch_bounds__(256) void k_tokenize(TokArgs a) {
           v[u] = (i[h] + u < n[h] && last_bad < u) ? code : R4;
         }
       }
-      *reinterpret_cast<uint4*>(out[h]) = make_uint4(v[0] << sh, v[1] << sh, v[2] << sh, v[3] << sh);
+#pragma unroll
+      for (int g = 0; g < TPG / 4; ++g)
+        reinterpret_cast<uint4*>(out[h])[g] =
+            make_uint4(v[4 * g] << sh, v[4 * g + 1] << sh, v[4 * g + 2] << sh, v[4 * g + 3] << sh);
     }
   }
 }
@@ -152,7 +157,7 @@ __global__ __launch_bounds__(256) void k_tokenize(TokArgs a) {
 // With a.dyn set, a.n_reads / a.n_bases are the capacities the grid is sized for.
 hipError_t launch_tokenize(const TokArgs& a, hipStream_t s) {
   if (a.n_reads == 0) return hipSuccess;
-  // groups of four entries are written with 16-byte stores
+  // entries are written with 16-byte stores
   if (reinterpret_cast<uintptr_t>(a.tokens) & 15u) return hipErrorInvalidValue;
   const uint64_t reads_per_block = 4ull * kTokReads;
   const uint64_t blocks = (a.n_reads + reads_per_block - 1) / reads_per_block;
