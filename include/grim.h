@@ -16,8 +16,9 @@
  *   - "device" buffers are HIP device memory on the device that holds the
  *     index; "host" buffers are ordinary process memory.
  *   - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
- *     Work is enqueued on that stream; every call below returns after its
- *     work on the stream is complete, so outputs are ready on return.
+ *     Work is enqueued on that stream; unless its comment says otherwise
+ *     (grim_mask_summary, the batcher and the server), a call returns after
+ *     its work on the stream is complete, so outputs are ready on return.
  *   - Bases are ASCII bytes; A, C, G, T are accepted in either case; any
  *     other byte (N, ...) makes every token window that holds it invalid.
  */
