@@ -377,31 +377,38 @@ def verify_leg(args, w, ref, rd, me, ep, reads, idx, cand, d_co, d_cb, pas, stre
                       "equivalent_cells_per_s": cells / (bounded_ms * 1e-3),
                       "equal_to_min_exact_E_plus_1": consistent}
     if not args.no_cpu_baseline:
-        from oracle import Oracle
-        o = Oracle()
-        rng = np.random.default_rng(4321)
-        ids = np.sort(rng.choice(rd.n, size=min(rd.n, 400), replace=False))
-        sub = rd.subset(ids)
-        sco = np.zeros(len(ids) + 1, np.int64)
-        sco[1:] = np.cumsum(co[ids + 1] - co[ids])
-        pick = np.concatenate([np.arange(co[i], co[i + 1]) for i in ids])
-        tsel = torch.from_numpy(pick).cuda()
-        mask = pas[tsel].cpu().numpy()
-        t = time.perf_counter()
-        wd, wm = o.verify(ref, w.bin_size, w.overlap, w.q, sub.bases, sub.offsets, sco, cb[pick], verify_mask=mask,
-                          max_edits=None if me is None else me[ids], err_pm_per_read=None if ep is None else ep[ids])
-        dt = time.perf_counter() - t
-        gd = dist.view(torch.int16)[tsel].cpu().numpy().view(np.uint16)
-        gm = match[tsel].cpu().numpy()
-        sub_cells = int(sum(int(sub.lengths[np.searchsorted(sco, k, side="right") - 1]) for k in
-                            np.nonzero(mask)[0])) * span
-        res["cpu_oracle"] = {"gcups": sub_cells / dt / 1e9, "cores": o.threads_used(), "kind": "oracle",
-                             "sample": f"{len(ids)} reads (seeded), {int(mask.sum())} passing pairs aligned",
-                             "seconds": dt, "gpu_bit_exact_on_sample": bool(np.array_equal(gd, wd) and
-                                                                           np.array_equal(gm, wm))}
-        log(f"verify oracle: {int(mask.sum())} pairs in {dt:.1f}s; GPU bit-exact: "
-            f"{res['cpu_oracle']['gpu_bit_exact_on_sample']}")
+        res["cpu_baseline"] = verify_cpu_baseline(w, ref, rd, me, ep, cand, pas, dist, match, span)
+        log(f"verify oracle: {res['cpu_baseline']['sample']}; GPU bit-exact: "
+            f"{res['cpu_baseline']['gpu_bit_exact_on_sample']}")
     return res
+
+
+def verify_cpu_baseline(w, ref, rd, me, ep, cand, pas, dist, match, span):
+    """The CPU baseline of verification: the oracle's dynamic program timed on a seeded
+    sample of reads (their passing pairs), and checked against the GPU's distances."""
+    import torch
+    from oracle import Oracle
+    co, cb = cand
+    o = Oracle()
+    rng = np.random.default_rng(4321)
+    ids = np.sort(rng.choice(rd.n, size=min(rd.n, 400), replace=False))
+    sub = rd.subset(ids)
+    sco = np.zeros(len(ids) + 1, np.int64)
+    sco[1:] = np.cumsum(co[ids + 1] - co[ids])
+    pick = np.concatenate([np.arange(co[i], co[i + 1]) for i in ids])
+    tsel = torch.from_numpy(pick).cuda()
+    mask = pas[tsel].cpu().numpy()
+    t = time.perf_counter()
+    wd, wm = o.verify(ref, w.bin_size, w.overlap, w.q, sub.bases, sub.offsets, sco, cb[pick], verify_mask=mask,
+                      max_edits=None if me is None else me[ids], err_pm_per_read=None if ep is None else ep[ids])
+    dt = time.perf_counter() - t
+    gd = dist.view(torch.int16)[tsel].cpu().numpy().view(np.uint16)
+    gm = match[tsel].cpu().numpy()
+    sub_cells = int(sum(int(sub.lengths[np.searchsorted(sco, k, side="right") - 1]) for k in
+                        np.nonzero(mask)[0])) * span
+    return {"value": sub_cells / dt / 1e9, "unit": "GCUPS", "cores": o.threads_used(), "kind": "oracle",
+            "sample": f"{len(ids)} reads (seeded), {int(mask.sum())} passing pairs aligned", "seconds": dt,
+            "gpu_bit_exact_on_sample": bool(np.array_equal(gd, wd) and np.array_equal(gm, wm))}
 
 
 def seeding_leg(args, w, ref, rd, d_bases, d_offs, d_co, d_cb, cpu_seed_s, stream):
