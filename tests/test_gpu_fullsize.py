@@ -51,7 +51,7 @@ def test_c3_full_size(oracle, human_genome):
     bit = (words >> (tb % 32).to(torch.int32)) & 1
     assert int(bit.sum().item()) == rd.n
     # a seeded sample of rows against the oracle, every bin
-    ids = np.sort(np.random.default_rng(31).choice(rd.n, size=48, replace=False))
+    ids = np.sort(np.random.default_rng(31).choice(rd.n, size=256, replace=False))
     got = host(mask.view(torch.int32)[torch.from_numpy(ids).cuda()]).view(np.uint32)
     del mask, words, bit
     torch.cuda.empty_cache()
