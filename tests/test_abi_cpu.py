@@ -200,3 +200,12 @@ int main(void){
                                                  ctypes.sizeof(grim.BatchBuffers)]
     assert [int(x) for x in lines[1].split()] == [grim.ServeConfig.flags.offset, grim.Result.latency_ms.offset,
                                                  grim.ServeStats.reads_per_s.offset]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on exactly one GPU and says so (before touching any device)."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert p.returncode == 2 and "exactly one GPU" in p.stderr
