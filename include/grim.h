@@ -158,9 +158,10 @@ void grim_index_free(grim_index* idx);
  *               is pass[r][x]; bits at x >= n_bins are 0.
  *   counts_out  device, NULL or [n_reads][n_bins] counts of counts_bytes each
  *               (1: uint8, every read must have L - q + 1 <= 255; 2: uint16).
- * Errors: GRIM_EINVAL (layout missing, L_r < q, bad offsets, counts_bytes),
- *         GRIM_EOVERLAP (see GRIM_READS_ALLOW_SHORT_OVERLAP). On error the
- *         outputs are left unwritten. */
+ * Errors: GRIM_EINVAL (layout missing, L_r < q, more than 65535 tokens in a
+ *         read, bad offsets, counts_bytes), GRIM_EOVERLAP (see
+ *         GRIM_READS_ALLOW_SHORT_OVERLAP). On error the outputs are left
+ *         unwritten. */
 int grim_filter_scan(const grim_index* idx, const grim_reads* reads, uint32_t* mask_out,
                      void* counts_out, uint32_t counts_bytes, void* hip_stream);
 
