@@ -258,6 +258,18 @@ __device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lan
   uint32_t km[NP];
 #pragma unroll
   for (int k = 0; k < NP; ++k) km[k] = ((K >> k) & 1u) ? 0xFFFFFFFFu : 0u;
+  if (!COUNTS && gw0 + LW < a.W) {
+    // every word of the lane is a whole word of the row: no range or tail checks
+    uint32_t* o = out_row + gw0;
+#pragma unroll
+    for (int j = 0; j < LW; ++j) {
+      uint32_t pl[NP];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) pl[k] = c.p[k][j];
+      o[j] = ge_threshold<NP>(pl, km, allpass);
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < LW; ++j) {
     const uint64_t gw = gw0 + j;

@@ -143,6 +143,9 @@ def test_scan_matches_oracle_random(oracle, seed, monkeypatch):
     m, c = gpu_scan(idx, rd, counts_dtype=__import__("torch").uint16, **kw)
     assert np.array_equal(c.astype(np.uint16), want_c)
     assert np.array_equal(unpack_mask(m, nb), want_p)
+    # the mask-only kernel (no count output compiled in) writes the same bits
+    m2, _ = gpu_scan(idx, rd, **kw)
+    assert np.array_equal(m2, m)
     # mask bits beyond the last bin are zero
     if nb % 32:
         assert not (m[:, -1] >> (nb % 32)).any()
