@@ -92,6 +92,8 @@ def test_scan_rejects_null_arguments():
     assert L.grim_filter_scan(None, ctypes.byref(r), None, None, 0, None) == grim.GRIM_EINVAL
     assert L.grim_filter_candidates(None, ctypes.byref(r), None, None, 0, None, None, None) == grim.GRIM_EINVAL
     assert L.grim_verify_candidates(None, ctypes.byref(r), None, None, 0, None, None, None, None) == grim.GRIM_EINVAL
+    assert L.grim_verify_candidates_bounded(None, ctypes.byref(r), None, None, 0, None, None, None,
+                                            None) == grim.GRIM_EINVAL
     n = ctypes.c_uint64()
     assert L.grim_seed_candidates(None, ctypes.byref(r), 2048, 8, None, None, ctypes.byref(n), None) == grim.GRIM_EINVAL
     assert L.grim_seeds_info(None, None) == grim.GRIM_EINVAL
