@@ -256,18 +256,45 @@ __global__ __launch_bounds__(256) void k_seed_select(CandArgs2 a) {
     for (uint32_t j = lane; j < nr; j += 64) a.cand_bin[out0 + j] = (int32_t)rb[j];
     return;
   }
-  // the largest v with at least cap runs of >= v votes (bisection)
+  // the largest v with at least cap runs of >= v votes: one pass counts the
+  // runs at or above every v up to 32 (votes are few: one per seed); larger
+  // thresholds fall back to a bisection
+  constexpr uint32_t kHist = 32;
+  uint32_t ge[kHist + 1];
+#pragma unroll
+  for (uint32_t t = 0; t <= kHist; ++t) ge[t] = 0;
   uint32_t vmax = 0;
-  for (uint32_t j = lane; j < nr; j += 64) vmax = max(vmax, run_votes(rs, j, nr, s1));
+  for (uint32_t j0 = 0; j0 < nr; j0 += 64) {
+    const uint32_t j = j0 + lane;
+    const uint32_t v = j < nr ? run_votes(rs, j, nr, s1) : 0u;
+    vmax = max(vmax, v);
+#pragma unroll
+    for (uint32_t t = 1; t <= kHist; ++t) ge[t] += (uint32_t)__popcll(__ballot(v >= t));
+  }
   for (int off = 32; off >= 1; off >>= 1) vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, off));
   uint32_t lo = 1, hi = vmax;
+  if (ge[kHist] < a.cap) {
+    // the threshold is at most 32: the largest t with ge[t] >= cap (ge[1] = nr > cap)
+    uint32_t vt1 = 1;
+#pragma unroll
+    for (uint32_t t = 2; t <= kHist; ++t)
+      if (ge[t] >= a.cap) vt1 = t;
+    lo = hi = vt1;
+  } else {
+    lo = kHist;
+  }
   while (lo < hi) {
     const uint32_t mid = lo + (hi - lo + 1) / 2;
     if (count_at_least(rs, nr, s1, mid, lane) >= a.cap) lo = mid;
     else hi = mid - 1;
   }
   const uint32_t vt = lo;
-  const uint32_t need = a.cap - count_at_least(rs, nr, s1, vt + 1, lane);  // runs taken at exactly vt
+  // runs taken at exactly vt (ge is read with static indexes only, so it stays in registers)
+  uint32_t above = 0;
+#pragma unroll
+  for (uint32_t t = 2; t <= kHist; ++t)
+    if (t == vt + 1) above = ge[t];
+  const uint32_t need = a.cap - (vt < kHist ? above : count_at_least(rs, nr, s1, vt + 1, lane));
   uint32_t taken = 0, ties = 0;
   for (uint32_t j0 = 0; j0 < nr; j0 += 64) {
     const uint32_t j = j0 + lane;
