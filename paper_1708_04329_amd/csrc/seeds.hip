@@ -183,15 +183,31 @@ __global__ __launch_bounds__(256) void k_seed_expand(CandArgs2 a) {
   const uint8_t* rd = a.bases + a.offsets[r];
   const int64_t L = a.offsets[r + 1] - a.offsets[r];
   uint64_t w = a.seg[i];
-  for (int64_t o = 0; o + (int64_t)a.k <= L; o += a.k) {
-    const int64_t c = seed_code(rd + o, a.k);
-    if (c < 0) continue;
-    const uint64_t h0 = a.start[c], h1 = a.start[c + 1];
-    for (uint64_t h = h0 + lane; h < h1; h += 64) {
-      const int64_t loc = (int64_t)a.pos[h] - o;
-      a.keys_a[w + (h - h0)] = (uint32_t)((loc < 0 ? 0 : loc) / a.B);
+  const int64_t n_seeds = L >= (int64_t)a.k ? L / (int64_t)a.k : 0;
+  // up to 64 seeds at a time: lane j codes seed sb + j and looks up its hit
+  // range, all in parallel; then the wavefront writes each seed's hits
+  for (int64_t sb = 0; sb < n_seeds; sb += 64) {
+    uint64_t h0 = 0, h1 = 0;
+    if (sb + lane < n_seeds) {
+      const int64_t c = seed_code(rd + (sb + lane) * a.k, a.k);
+      if (c >= 0) {
+        h0 = a.start[c];
+        h1 = a.start[c + 1];
+      }
     }
-    w += h1 - h0;
+    const int64_t m = min<int64_t>(64, n_seeds - sb);
+    for (int64_t j = 0; j < m; ++j) {
+      const uint64_t H0 = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(h0 >> 32), (int)j) << 32) |
+                          (uint32_t)__shfl((int)(uint32_t)h0, (int)j);
+      const uint64_t H1 = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(h1 >> 32), (int)j) << 32) |
+                          (uint32_t)__shfl((int)(uint32_t)h1, (int)j);
+      const int64_t o = (sb + j) * (int64_t)a.k;
+      for (uint64_t h = H0 + lane; h < H1; h += 64) {
+        const int64_t loc = (int64_t)a.pos[h] - o;
+        a.keys_a[w + (h - H0)] = (uint32_t)((loc < 0 ? 0 : loc) / a.B);
+      }
+      w += H1 - H0;
+    }
   }
 }
 
