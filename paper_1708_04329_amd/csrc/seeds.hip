@@ -49,6 +49,7 @@ struct grim_seeds {
   uint64_t hits_cap = 0, hits_host_cap = 0;
   uint32_t* seg = nullptr;        // [batch reads + 1] segment offsets
   uint32_t* cnt = nullptr;        // [batch reads + 1] runs kept per read
+  uint32_t* nruns = nullptr;      // [batch reads + 1] runs per read
   uint64_t* outoff = nullptr;     // [batch reads + 1] first output slot (batch-relative)
   uint64_t batch_cap = 0;
   uint32_t* keys_a = nullptr;     // [batch keys] bins, then run start positions
@@ -148,6 +149,7 @@ struct CandArgs2 {
   uint32_t* keys_b;
   uint32_t* runs;
   uint32_t* cnt;
+  uint32_t* nruns;
   const uint64_t* outoff;
   uint64_t out_base;      // output slot of the batch's first candidate
   int64_t* cand_off;
@@ -233,7 +235,10 @@ __global__ __launch_bounds__(256) void k_seed_runs(CandArgs2 a) {
     }
     nr += (uint32_t)__popcll(m);
   }
-  if (lane == 0) a.cnt[i] = min(nr, a.cap);
+  if (lane == 0) {
+    a.cnt[i] = min(nr, a.cap);
+    a.nruns[i] = nr;
+  }
 }
 
 // Votes of run j of a read whose runs start at rs[0 .. nr) within [.., s1).
@@ -260,12 +265,7 @@ __global__ __launch_bounds__(256) void k_seed_select(CandArgs2 a) {
   const uint32_t s0 = a.seg[i], s1 = a.seg[i + 1];
   const uint64_t out0 = a.out_base + a.outoff[i];
   if (lane == 0) a.cand_off[r] = (int64_t)out0;
-  // number of runs: recount the run starts (cnt holds min(runs, cap))
-  uint32_t nr = 0;
-  for (uint32_t c0 = s0; c0 < s1; c0 += 64) {
-    const uint32_t idx = c0 + lane;
-    nr += (uint32_t)__popcll(__ballot(idx < s1 && (idx == s0 || a.keys_b[idx - 1] != a.keys_b[idx])));
-  }
+  const uint32_t nr = a.nruns[i];  // runs of the read (cnt holds min(runs, cap))
   const uint32_t* rs = a.keys_a + s0;
   const uint32_t* rb = a.runs + s0;
   if (nr <= a.cap) {
@@ -373,7 +373,7 @@ void free_seeds(grim_seeds* sd) {
   if (!sd) return;
   SeedGuard g(sd->device);
   for (void* p : {(void*)sd->start, (void*)sd->pos, (void*)sd->hits, (void*)sd->seg, (void*)sd->cnt,
-                  (void*)sd->outoff, (void*)sd->keys_a, (void*)sd->keys_b, (void*)sd->runs, sd->tmp,
+                  (void*)sd->nruns, (void*)sd->outoff, (void*)sd->keys_a, (void*)sd->keys_b, (void*)sd->runs, sd->tmp,
                   (void*)sd->staging})
     if (p) (void)hipFree(p);
   if (sd->hits_host) (void)hipHostFree(sd->hits_host);
@@ -547,14 +547,16 @@ int grim_seed_candidates(const grim_seeds* csd, const grim_reads* rd, uint32_t b
     seg_host.assign(nb + 1, 0);
     for (uint64_t i = 0; i < nb; ++i) seg_host[i + 1] = seg_host[i] + (uint32_t)H[r0 + i];
     if (sd->batch_cap < nb + 1 || !sd->seg) {
-      for (void* p : {(void*)sd->seg, (void*)sd->cnt, (void*)sd->outoff})
+      for (void* p : {(void*)sd->seg, (void*)sd->cnt, (void*)sd->nruns, (void*)sd->outoff})
         if (p) (void)hipFree(p);
       sd->seg = nullptr;
       sd->cnt = nullptr;
+      sd->nruns = nullptr;
       sd->outoff = nullptr;
-      uint64_t c0 = 0, c1 = 0, c2 = 0;
+      uint64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
       if ((rc = grow_dev(&sd->seg, &c0, nb + 1))) return rc;
       if ((rc = grow_dev(&sd->cnt, &c1, c0))) return rc;
+      if ((rc = grow_dev(&sd->nruns, &c3, c0))) return rc;
       if ((rc = grow_dev(&sd->outoff, &c2, c0))) return rc;
       sd->batch_cap = c0;
     }
@@ -588,6 +590,7 @@ int grim_seed_candidates(const grim_seeds* csd, const grim_reads* rd, uint32_t b
     a.keys_b = sd->keys_b;
     a.runs = sd->runs;
     a.cnt = sd->cnt;
+    a.nruns = sd->nruns;
     a.outoff = sd->outoff;
     a.out_base = out_base;
     a.cand_off = cand_off;
