@@ -108,20 +108,61 @@ __device__ __forceinline__ void for_kmers(const uint8_t* ref, uint64_t G, uint32
   }
 }
 
+// The same walk with the thread's bytes loaded up front: 80 bytes in five 16-byte loads (64
+// start positions plus up to 13 more bases for k <= 14), the bases then coded without
+// branches. Needs a 16-byte aligned reference; a thread whose 80 bytes run past the end takes
+// the byte-wise walk.
+template <typename F>
+__device__ __forceinline__ void for_kmers_vec(const uint8_t* ref, uint64_t G, uint32_t k, uint64_t p0, F f) {
+  constexpr uint32_t kBytes = 80;
+  if (p0 + kBytes > G) {
+    for_kmers(ref, G, k, p0, f);
+    return;
+  }
+  uint4 v[kBytes / 16];
+  const uint4* src = reinterpret_cast<const uint4*>(ref + p0);
+#pragma unroll
+  for (uint32_t j = 0; j < kBytes / 16; ++j) v[j] = src[j];
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(v);
+  const uint64_t mask = (1ull << (2 * k)) - 1ull;  // k <= 14
+  const uint32_t end = kSpan + k - 1;
+  uint64_t code = 0;
+  uint32_t run = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kBytes; ++i) {
+    if (i >= end) break;
+    const uint32_t d = (((w[i >> 2] >> (8 * (i & 3))) & 0xFFu) | 0x20u) - 0x60u;  // 'a' -> 1 ... 't' -> 20
+    const bool ok = d < 32u && ((0x0010008Au >> d) & 1u);                        // a, c, g, t
+    run = ok ? run + 1 : 0;
+    code = ((code << 2) | (uint64_t)(((d >> 1) ^ (d >> 2)) & 3u)) & mask;       // a0 c1 g2 t3
+    if (run >= k) f(code, p0 + i + 1 - k);
+  }
+}
+
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_kmer_count(const uint8_t* ref, uint64_t G, uint32_t k, uint32_t* counts) {
   const uint64_t p0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kSpan;
   if (p0 + k > G) return;
-  for_kmers(ref, G, k, p0, [&](uint64_t code, uint64_t) { atomicAdd(&counts[code], 1u); });
+  auto visit = [&](uint64_t code, uint64_t) { atomicAdd(&counts[code], 1u); };
+  if (VEC)
+    for_kmers_vec(ref, G, k, p0, visit);
+  else
+    for_kmers(ref, G, k, p0, visit);
 }
 
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_kmer_fill(const uint8_t* ref, uint64_t G, uint32_t k,
                                                    const uint64_t* start, uint32_t* counts, uint32_t* pos) {
   const uint64_t p0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kSpan;
   if (p0 + k > G) return;
-  for_kmers(ref, G, k, p0, [&](uint64_t code, uint64_t p) {
+  auto visit = [&](uint64_t code, uint64_t p) {
     const uint32_t left = atomicSub(&counts[code], 1u);  // in [1, count]
     pos[start[code] + left - 1] = (uint32_t)p;
-  });
+  };
+  if (VEC)
+    for_kmers_vec(ref, G, k, p0, visit);
+  else
+    for_kmers(ref, G, k, p0, visit);
 }
 
 // Code of the k bases at s, or -1 if one is not A, C, G, T.
@@ -441,7 +482,9 @@ int grim_seeds_build(const uint8_t* ref, uint64_t ref_len, uint32_t ref_on_devic
   if ((e = launch_zero_words(counts, (uint32_t)(sd->nk + 1), s)) != hipSuccess) return fail(e, "zero counts");
   const uint64_t threads = (ref_len + kSpan - 1) / kSpan;
   const uint64_t blocks = (threads + 255) / 256;
-  hipLaunchKernelGGL(k_kmer_count, dim3((unsigned)blocks), dim3(256), 0, s, dref, ref_len, k, counts);
+  const bool vec = ((uintptr_t)dref & 15u) == 0;
+  hipLaunchKernelGGL(vec ? k_kmer_count<true> : k_kmer_count<false>, dim3((unsigned)blocks), dim3(256), 0, s, dref,
+                     ref_len, k, counts);
   if ((e = hipGetLastError()) != hipSuccess) return fail(e, "k-mer count");
   size_t tmp_bytes = 0;
   if ((e = rocprim::exclusive_scan(nullptr, tmp_bytes, counts, sd->start, (uint64_t)0, (size_t)(sd->nk + 1),
@@ -458,8 +501,8 @@ int grim_seeds_build(const uint8_t* ref, uint64_t ref_len, uint32_t ref_on_devic
   sd->n_pos = n_pos;
   if ((e = hipMalloc(&sd->pos, std::max<uint64_t>(n_pos, 1) * sizeof(uint32_t))) != hipSuccess)
     return fail(e, "positions");
-  hipLaunchKernelGGL(k_kmer_fill, dim3((unsigned)blocks), dim3(256), 0, s, dref, ref_len, k, sd->start, counts,
-                     sd->pos);
+  hipLaunchKernelGGL(vec ? k_kmer_fill<true> : k_kmer_fill<false>, dim3((unsigned)blocks), dim3(256), 0, s, dref,
+                     ref_len, k, sd->start, counts, sd->pos);
   if ((e = hipGetLastError()) != hipSuccess) return fail(e, "k-mer fill");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "k-mer fill");
   cleanup();
