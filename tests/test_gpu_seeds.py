@@ -72,6 +72,34 @@ def test_seed_candidates_match_oracle_random(oracle, k, B, cap):
     assert np.array_equal(got_h[0], want[0]) and np.array_equal(got_h[1], want[1])
 
 
+@pytest.mark.parametrize("k", [12, 14])
+def test_seed_table_reference_placement(oracle, k):
+    """The table passes load a 16-byte aligned reference in 16-byte pieces and walk any other
+    reference byte by byte: a device reference one byte off alignment and a host reference
+    (staged into aligned device memory) give the oracle's lists, as the aligned one does."""
+    import torch
+    rng = random.Random(70 + k)
+    ref = rand_genome(rng, 150_003)
+    rd = rand_reads(rng, ref, 300)
+    want = oracle.seed_candidates(ref, rd.bases, rd.offsets, k, 1500, 40)
+    padded = dev(np.concatenate([np.frombuffer(b"A", np.uint8), ref]))
+    shifted = padded[1:]
+    assert shifted.data_ptr() % 16 != 0
+    for name, r in (("aligned", dev(ref)), ("unaligned", shifted), ("host", ref)):
+        seeds = grim.grim_seeds_build(r, k)
+        assert seeds.info()["n_positions"] == int(oracle_positions(ref, k)), name
+        got = gpu_candidates(seeds, rd, 1500, 40)
+        torch.cuda.synchronize()
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), name
+
+
+def oracle_positions(ref: np.ndarray, k: int) -> int:
+    """Reference positions whose k bases are all A, C, G or T (either case)."""
+    ok = np.isin(ref | 0x20, np.frombuffer(b"acgt", np.uint8)).astype(np.int64)
+    run = np.convolve(ok, np.ones(k, np.int64), mode="valid")
+    return int((run == k).sum())
+
+
 def test_seed_candidates_many_batches(oracle, monkeypatch):
     rng = random.Random(5)
     ref = rand_genome(rng, 100_000)
