@@ -227,6 +227,11 @@ typedef struct {
  *   ref, ref_len   reference bases (host, or device if ref_on_device = 1);
  *                  ref_len < 2^32 (positions are stored as uint32)
  *   k              seed length in [1, 14]
+ * Positions within a bucket are in no fixed order; the candidate lists do
+ * not depend on it. Any alignment of ref is accepted; a 16-byte aligned
+ * device reference (and every host one, which is staged) is read with
+ * 16-byte loads. The call returns once the table is built, and ref is not
+ * kept.
  * Errors: GRIM_EINVAL, GRIM_ENOMEM, GRIM_EDEVICE. */
 int grim_seeds_build(const uint8_t* ref, uint64_t ref_len, uint32_t ref_on_device, uint32_t k, void* hip_stream,
                      grim_seeds** out);
