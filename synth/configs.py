@@ -11,7 +11,7 @@ substitution:insertion:deletion = 8:1:1 unless stated.
 
 from __future__ import annotations
 
-from dataclasses import dataclass, field, replace
+from dataclasses import dataclass, replace
 from typing import Optional
 
 from . import MASTER_SEED, GenomeSpec, ReadSpec
