@@ -100,6 +100,26 @@ def oracle_positions(ref: np.ndarray, k: int) -> int:
     return int((run == k).sum())
 
 
+@pytest.mark.parametrize("cap", [1, 7, 40])
+def test_seed_threshold_above_32_votes(oracle, cap):
+    """Short seeds (k = 2) on a small genome give every bin hundreds of votes, so the kept
+    bins' vote threshold lies far above 32: the selection takes its bisection path there."""
+    rng = random.Random(31 + cap)
+    ref = np.frombuffer(bytes(rng.choice(b"ACGT") for _ in range(20_000)), np.uint8).copy()
+    seqs = []
+    for _ in range(120):
+        L = rng.randrange(60, 200)
+        p = rng.randrange(len(ref) - L)
+        seqs.append(ref[p:p + L].tobytes())
+    rd = synth.reads_from_strings(seqs)
+    want = oracle.seed_candidates(ref, rd.bases, rd.offsets, 2, 256, cap)
+    lens = np.diff(want[0])
+    assert (lens == cap).all()  # every read keeps cap of its ~79 voted bins
+    seeds = grim.grim_seeds_build(dev(ref), 2)
+    got = gpu_candidates(seeds, rd, 256, cap)
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+
+
 def test_seed_candidates_many_batches(oracle, monkeypatch):
     rng = random.Random(5)
     ref = rand_genome(rng, 100_000)
