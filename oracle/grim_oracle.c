@@ -157,15 +157,21 @@ uint32_t oracle_count(const uint8_t* bits_of_bin, const uint8_t* read, uint32_t 
   return count;
 }
 
+/* Error budget E_r of read r: the explicit per-read value if given, else the
+ * ceiling rule on the read's own rate, else on the rate shared by all reads. */
+static uint32_t read_budget(const int64_t* offsets, uint64_t r, const uint16_t* max_edits,
+                            const uint16_t* err_pm_per_read, uint32_t err_permille) {
+  uint32_t L = (uint32_t)(offsets[r + 1] - offsets[r]);
+  if (max_edits) return max_edits[r];
+  if (err_pm_per_read) return oracle_max_edits(L, err_pm_per_read[r]);
+  return oracle_max_edits(L, err_permille);
+}
+
 static int64_t read_threshold(const int64_t* offsets, uint64_t r, uint32_t q,
                               const uint16_t* max_edits, const uint16_t* err_pm_per_read,
                               uint32_t err_permille) {
   uint32_t L = (uint32_t)(offsets[r + 1] - offsets[r]);
-  uint32_t E;
-  if (max_edits) E = max_edits[r];
-  else if (err_pm_per_read) E = oracle_max_edits(L, err_pm_per_read[r]);
-  else E = oracle_max_edits(L, err_permille);
-  return oracle_threshold(L, q, E);
+  return oracle_threshold(L, q, read_budget(offsets, r, max_edits, err_pm_per_read, err_permille));
 }
 
 /* Threshold of every read, for checking the GPU's per-read threshold table. */
@@ -272,10 +278,7 @@ int oracle_verify(const uint8_t* ref, uint64_t G, uint32_t B, uint32_t O, uint32
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
   for (int64_t r = 0; r < (int64_t)n; ++r) {
     const uint32_t L = (uint32_t)(offsets[r + 1] - offsets[r]);
-    uint32_t E;
-    if (max_edits) E = max_edits[r];
-    else if (err_pm_per_read) E = oracle_max_edits(L, err_pm_per_read[r]);
-    else E = oracle_max_edits(L, err_permille);
+    const uint32_t E = read_budget(offsets, (uint64_t)r, max_edits, err_pm_per_read, err_permille);
     for (int64_t k = cand_off[r]; k < cand_off[r + 1]; ++k) {
       const int32_t x = cand_bin[k];
       if (x < 0 || (uint64_t)x >= nb) { bad = 1; continue; }
@@ -286,13 +289,36 @@ int oracle_verify(const uint8_t* ref, uint64_t G, uint32_t B, uint32_t O, uint32
       }
       uint64_t lo, hi;
       oracle_bin_bases((uint64_t)x, G, B, O, q, &lo, &hi);
-      uint32_t d = oracle_semiglobal_distance(bases + offsets[r], L, ref + lo, hi - lo);
-      if (d > 0xFFFE) d = 0xFFFE;
-      dist[k] = (uint16_t)d;
+      const uint32_t d = oracle_semiglobal_distance(bases + offsets[r], L, ref + lo, hi - lo);
+      dist[k] = (uint16_t)(d > 0xFFFE ? 0xFFFE : d);
       match[k] = d <= E ? 1 : 0;
     }
   }
   return bad ? -1 : 0;
+}
+
+/* Bounded verification: as oracle_verify, but an aligned pair whose distance
+ * exceeds the read's budget E_r reads E_r + 1 (at most 0xFFFE). A mapper's
+ * verification only has to decide whether the location maps within E_r
+ * (Section 1, seed-and-extend step 5), so distances past the budget carry no
+ * more information than "over". Skipped pairs keep 0xFFFF; match flags are
+ * oracle_verify's. */
+int oracle_verify_bounded(const uint8_t* ref, uint64_t G, uint32_t B, uint32_t O, uint32_t q,
+                          const uint8_t* bases, const int64_t* offsets, uint64_t n, const uint16_t* max_edits,
+                          const uint16_t* err_pm_per_read, uint32_t err_permille, const int64_t* cand_off,
+                          const int32_t* cand_bin, const uint8_t* verify_mask, uint16_t* dist, uint8_t* match,
+                          int nthreads) {
+  int rc = oracle_verify(ref, G, B, O, q, bases, offsets, n, max_edits, err_pm_per_read, err_permille, cand_off,
+                         cand_bin, verify_mask, dist, match, nthreads);
+  if (rc != 0) return rc;
+  for (uint64_t r = 0; r < n; ++r) {
+    const uint32_t E = read_budget(offsets, r, max_edits, err_pm_per_read, err_permille);
+    for (int64_t k = cand_off[r]; k < cand_off[r + 1]; ++k) {
+      if (dist[k] == 0xFFFF) continue; /* not aligned */
+      if (dist[k] > E) dist[k] = (uint16_t)(E + 1 < 0xFFFE ? E + 1 : 0xFFFE);
+    }
+  }
+  return 0;
 }
 
 /* One reference k-mer occurrence: code and start position. */

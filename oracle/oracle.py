@@ -89,6 +89,8 @@ def load(path: str = _LIB):
     lib.oracle_bin_bases.restype = None
     lib.oracle_verify.argtypes = [P, U64, U32, U32, U32, P, P, U64, P, P, U32, P, P, P, P, P, I]
     lib.oracle_verify.restype = I
+    lib.oracle_verify_bounded.argtypes = [P, U64, U32, U32, U32, P, P, U64, P, P, U32, P, P, P, P, P, I]
+    lib.oracle_verify_bounded.restype = I
     lib.oracle_seed_candidates.argtypes = [P, U64, P, P, U64, U32, U32, U32, P, P]
     lib.oracle_seed_candidates.restype = I64
     lib.oracle_threads.argtypes = [I]
@@ -251,9 +253,10 @@ class Oracle:
         return lo.value, hi.value
 
     def verify(self, ref, B: int, O: int, q: int, bases, offsets, cand_off, cand_bin, verify_mask=None,
-               max_edits=None, err_pm_per_read=None, err_permille: int = 0):
+               max_edits=None, err_pm_per_read=None, err_permille: int = 0, bounded: bool = False):
         """(dist uint16 [P], match uint8 [P]) in candidate (CSR) order; pairs whose
-        verify_mask entry is 0 get dist 0xFFFF and match 0."""
+        verify_mask entry is 0 get dist 0xFFFF and match 0. With ``bounded``, a
+        distance above the read's budget E_r reads E_r + 1 (at most 0xFFFE)."""
         ref = _u8(ref)
         bases = _u8(bases)
         offs = np.ascontiguousarray(offsets, np.int64)
@@ -265,8 +268,9 @@ class Oracle:
         P = len(cb)
         dist = np.empty(P, dtype=np.uint16)
         match = np.empty(P, dtype=np.uint8)
-        rc = self.lib.oracle_verify(_p(ref), len(ref), B, O, q, _p(bases), _p(offs), n, _p(me), _p(ep),
-                                    err_permille, _p(co), _p(cb), _p(vm), _p(dist), _p(match), self.threads)
+        fn = self.lib.oracle_verify_bounded if bounded else self.lib.oracle_verify
+        rc = fn(_p(ref), len(ref), B, O, q, _p(bases), _p(offs), n, _p(me), _p(ep), err_permille, _p(co), _p(cb),
+                _p(vm), _p(dist), _p(match), self.threads)
         if rc != 0:
             raise ValueError("candidate bin out of range")
         return dist, match
@@ -275,23 +279,8 @@ class Oracle:
                        max_edits=None, err_pm_per_read=None, err_permille: int = 0):
         """verify() with each distance above the read's budget E_r reported as E_r + 1
         (capped at 0xFFFE); match flags and skipped pairs (0xFFFF) unchanged."""
-        dist, match = self.verify(ref, B, O, q, bases, offsets, cand_off, cand_bin, verify_mask, max_edits,
-                                  err_pm_per_read, err_permille)
-        offs = np.ascontiguousarray(offsets, np.int64)
-        co = np.ascontiguousarray(cand_off, np.int64)
-        n = len(offs) - 1
-        for r in range(n):
-            L = int(offs[r + 1] - offs[r])
-            if max_edits is not None:
-                E = int(max_edits[r])
-            else:
-                e = int(err_pm_per_read[r]) if err_pm_per_read is not None else int(err_permille)
-                E = self.max_edits(L, e)
-            seg = slice(int(co[r]), int(co[r + 1]))
-            d = dist[seg]
-            over = (d != 0xFFFF) & (d.astype(np.int64) > E)
-            d[over] = min(E + 1, 0xFFFE)
-        return dist, match
+        return self.verify(ref, B, O, q, bases, offsets, cand_off, cand_bin, verify_mask, max_edits,
+                           err_pm_per_read, err_permille, bounded=True)
 
     def seed_candidates(self, ref, bases, offsets, k: int, B: int, cap: int):
         """(cand_off int64 [n+1], cand_bin int32 [n_cand]) of the seed-hit candidates."""

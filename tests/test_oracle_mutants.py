@@ -38,6 +38,9 @@ MUTANTS = {
     "verify_window_misses_last_token_bases": ("*hi = b > a ? b + q - 1 : a;", "*hi = b > a ? b : a;"),
     "verify_match_strict": ("match[k] = d <= E ? 1 : 0;", "match[k] = d < E ? 1 : 0;"),
     "verify_substitution_free": ("((rc >= 0 && rc == tc) ? 0u : 1u)", "0u"),
+    "verify_bounded_cap_at_budget": ("(uint16_t)(E + 1 < 0xFFFE ? E + 1 : 0xFFFE)", "(uint16_t)(E < 0xFFFE ? E : 0xFFFE)"),
+    "verify_bounded_overwrites_skipped": ("if (dist[k] == 0xFFFF) continue; /* not aligned */", ""),
+    "verify_bounded_global_rate_only": ("  if (err_pm_per_read) return oracle_max_edits(L, err_pm_per_read[r]);\n", ""),
     "seed_overlapping_seeds": ("o + (int64_t)k <= L; o += k)", "o + (int64_t)k <= L; o += 1)"),
     "seed_no_clamp_at_start": ("if (loc < 0) loc = 0;\n        if (nh", "if (nh"),
     "seed_rank_ties_to_larger_bin": ("return x->bin < y->bin ? -1 : (x->bin > y->bin ? 1 : 0);\n}\n\nstatic int cmp_bin",
@@ -46,6 +49,14 @@ MUTANTS = {
                                     "if (x->votes != y->votes) return x->votes < y->votes ? -1 : 1;"),
     "seed_n_seed_used": ("if (code < 0) continue;\n      /* first entry", "if (code < 0) code = 0;\n      /* first entry"),
 }
+
+BOUNDED_PIN_CALLS = [
+    lambda o: vpins.test_verify_bounded_explicit_budget(o),
+    lambda o: vpins.test_verify_bounded_ceiling_budget(o),
+    lambda o: vpins.test_verify_bounded_keeps_skipped_pairs(o),
+    lambda o: vpins.test_verify_bounded_largest_values(o),
+    *[(lambda o, s=s: vpins.test_verify_bounded_bruteforce(o, s)) for s in range(2)],
+]
 
 PIN_CALLS = [
     lambda o: pins.test_vector_length_q5(o),
@@ -70,6 +81,7 @@ PIN_CALLS = [
     lambda o: vpins.test_verify_window_edges(o),
     lambda o: vpins.test_verify_truth_locations(o),
     lambda o: vpins.test_verify_mask_skips_pairs(o),
+    *BOUNDED_PIN_CALLS,
     *[(lambda o, s=s: spins.test_seed_candidates_bruteforce(o, s)) for s in range(3)],
     lambda o: spins.test_seed_ties_cap_and_clamp(o),
 ]
@@ -98,5 +110,29 @@ def test_pins_catch_mutant(name):
             except (AssertionError, ValueError, IndexError):
                 caught += 1
         assert caught > 0, f"no pin catches mutant {name}"
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+
+
+# The mistakes a bounded verification could make: cap at E instead of E + 1,
+# take E with a floor, overwrite the skipped marker, ignore per-read rates.
+# The bounded pins alone must catch each of them.
+BOUNDED_MUTANTS = ["verify_bounded_cap_at_budget", "verify_bounded_overwrites_skipped",
+                   "verify_bounded_global_rate_only", "floor_error_budget"]
+
+
+@pytest.mark.parametrize("name", BOUNDED_MUTANTS)
+def test_bounded_pins_catch_mutant(name):
+    old, new = MUTANTS[name]
+    tmp = tempfile.mkdtemp(prefix="oracle_mutant_")
+    try:
+        mutant = Oracle(_build_mutant(tmp, old, new))
+        caught = 0
+        for call in BOUNDED_PIN_CALLS:
+            try:
+                call(mutant)
+            except (AssertionError, ValueError, IndexError):
+                caught += 1
+        assert caught > 0, f"no bounded-verification pin catches mutant {name}"
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
