@@ -114,10 +114,15 @@ const char* grim_last_error(void);
  * (0..3 for A, C, G, T in either case, 4 for any other byte), for
  * grim_verify_candidates.
  *   ref, ref_len   reference bases (host, or device if ref_on_device = 1)
- *   bin_size       B >= 1; overlap O >= 0; q in [1, 7]
+ *   bin_size       B >= 1; overlap O >= 0; q in [1, 8] (Section 6.1: a bin's
+ *                  vector has 4^q bits; uint16 token codes reach q = 8)
  *   out            receives a new handle, resident on the current HIP device
- * Errors: GRIM_EINVAL (bad sizes, ref_len < q, more than 2^31 bins),
- *         GRIM_ENOMEM, GRIM_EDEVICE. */
+ * The token-major layout (all-bins scan) takes q <= 7: it stages tiles of
+ * 4^q + 1 rows in the 160 KB of LDS of a CU, and at q = 8 even one 32-bin
+ * word per row (256 KB) does not fit. Candidate checks (GRIM_LAYOUT_BM, 8 KB
+ * vectors) and verification (GRIM_LAYOUT_REF) take q = 8.
+ * Errors: GRIM_EINVAL (bad sizes, ref_len < q, more than 2^31 bins,
+ *         GRIM_LAYOUT_TM with q = 8), GRIM_ENOMEM, GRIM_EDEVICE. */
 int grim_build_index(const uint8_t* ref, uint64_t ref_len, uint32_t ref_on_device,
                      uint32_t bin_size, uint32_t overlap, uint32_t q, uint32_t layout,
                      void* hip_stream, grim_index** out);
@@ -249,8 +254,10 @@ void grim_seeds_free(grim_seeds* seeds);
  *               entries are written
  *   n_cand_out  host, receives the number of candidates
  * Reads may be on the host or the device (grim_reads.on_device); their error
- * budgets are not used. Errors: GRIM_EINVAL, GRIM_ENOMEM (the seed hits of
- * one read exceed 2^32), GRIM_EDEVICE. */
+ * budgets are not used. Errors: GRIM_EINVAL (a NULL pointer, bin_size or cap
+ * 0, read offsets out of order or outside [0, n_bases]: nothing is written
+ * to cand_bin then), GRIM_ENOMEM (the seed hits of one read exceed 2^32),
+ * GRIM_EDEVICE. */
 int grim_seed_candidates(const grim_seeds* seeds, const grim_reads* reads, uint32_t bin_size, uint32_t cap,
                          int64_t* cand_off, int32_t* cand_bin, uint64_t* n_cand_out, void* hip_stream);
 
@@ -457,11 +464,17 @@ typedef struct {
  * Errors: GRIM_EINVAL, GRIM_ENOMEM (arena), GRIM_EDEVICE. */
 int grim_serve_create(const grim_index* idx, const grim_serve_config* cfg, grim_server** out);
 
-/* Queue a request; its reads (host memory, on_device = 0, offsets from 0 to
- * n_bases, flags = 0) are copied before the call returns. Errors:
- * GRIM_EINVAL, GRIM_ENOMEM (the request's footprint exceeds the whole arena,
- * so it could never be admitted), GRIM_EAGAIN (host staging full: retry after
- * completions). */
+/* Queue a request; its reads (offsets from 0 to n_bases, flags = 0) are
+ * copied into the server's pinned staging before the call returns, so the
+ * caller may reuse them at once. Host reads (on_device = 0) are copied with
+ * memcpy; device reads (on_device = 1, on the index's device) with
+ * synchronous device-to-host copies, so their producer must have finished.
+ * Errors: GRIM_EINVAL, GRIM_ENOMEM (the request's footprint exceeds the whole
+ * arena, so it could never be admitted), GRIM_EAGAIN (host staging full:
+ * retry after completions), GRIM_EDEVICE (the server stopped after a device
+ * failure, or a copy of device reads failed), GRIM_ECANCELED (shutting down).
+ * After a device failure every queued, prepared or waiting request ends with
+ * GRIM_EDEVICE; requests whose launches completed keep their results. */
 int grim_serve_submit(grim_server* s, const grim_reads* reads, uint64_t* ticket);
 
 /* Result of a request if it has ended (returns its status), else GRIM_EAGAIN. */

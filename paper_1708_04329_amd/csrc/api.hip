@@ -370,7 +370,10 @@ int grim_build_index(const uint8_t* ref, uint64_t ref_len, uint32_t ref_on_devic
   *out = nullptr;
   if (!ref) return set_error(GRIM_EINVAL, "ref is NULL");
   if (bin_size == 0) return set_error(GRIM_EINVAL, "bin_size must be >= 1");
-  if (q < 1 || q > 7) return set_error(GRIM_EINVAL, "q must be in [1, 7]");
+  if (q < 1 || q > 8) return set_error(GRIM_EINVAL, "q must be in [1, 8]");
+  if (q == 8 && (layout & GRIM_LAYOUT_TM))
+    return set_error(GRIM_EINVAL, "the token-major layout (all-bins scan) supports q <= 7: a tile of 4^8 + 1 rows "
+                                  "does not fit the 160 KB of LDS; use GRIM_LAYOUT_BM (candidate checks) at q = 8");
   if (ref_len < q) return set_error(GRIM_EINVAL, "reference shorter than q");
   if (layout == 0 || (layout & ~(GRIM_LAYOUT_TM | GRIM_LAYOUT_BM | GRIM_LAYOUT_REF)))
     return set_error(GRIM_EINVAL, "layout must be a combination of GRIM_LAYOUT_TM, GRIM_LAYOUT_BM, GRIM_LAYOUT_REF");
@@ -514,7 +517,7 @@ int grim_index_load(const char* path, void* hip_stream, grim_index** out) {
     return set_error(GRIM_EIO, "%s: not a GRIM index file of version %u", path, kFileVersion);
   }
   grim_index probe;
-  if (h.B == 0 || h.q < 1 || h.q > 7 || h.G < h.q || h.layout == 0 ||
+  if (h.B == 0 || h.q < 1 || h.q > 8 || (h.q == 8 && (h.layout & GRIM_LAYOUT_TM)) || h.G < h.q || h.layout == 0 ||
       (h.layout & ~(GRIM_LAYOUT_TM | GRIM_LAYOUT_BM | GRIM_LAYOUT_REF))) {
     std::fclose(f);
     return set_error(GRIM_EIO, "%s: bad parameters in header", path);

@@ -65,7 +65,7 @@ __device__ __forceinline__ uint32_t group_sum(uint32_t x) {
 template <int VW>
 __device__ __forceinline__ int build_planes(const CandArgs& a, uint64_t r, uint64_t n_cand, uint32_t* planes,
                                             uint32_t lane, int64_t* pc0, int64_t* pc1) {
-  static_assert(VW <= 512, "planes of 4^q bits");
+  static_assert(VW <= 2048, "planes of 4^q bits, q <= 8");
   constexpr uint32_t kWords = kMaxPlanes * VW;
   const int64_t c0 = a.cand_off[r], c1 = a.cand_off[r + 1];
   if (c0 < 0 || c1 < c0 || (uint64_t)c1 > n_cand) {
@@ -299,17 +299,21 @@ hipError_t launch_nw_layout(const CandArgs& a, const CandConfig& cfg, hipStream_
 
 template <int VW, int NW>
 hipError_t launch_nw(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
-  if constexpr (VW >= 32) {
+  // the cooperative layout needs a pair's vector within one wavefront's lanes
+  if constexpr (VW >= 32 && VW <= 512) {
     if (cfg.coop) return launch_nw_layout<VW, NW, true>(a, cfg, s);
   }
   return launch_nw_layout<VW, NW, false>(a, cfg, s);
 }
 
 // LDS per wavefront: 16 * VW words; the wave count per group is capped so a
-// group stays within 64 KB.
+// group stays within 64 KB, except at q = 8, where one wavefront's planes take
+// 128 KB of the 160 KB of a CU: one wavefront per group and per CU, each lane
+// streaming whole 8 KB vectors (a boundary case the paper's token lengths of
+// 4 to 6 do not reach).
 template <int VW>
 hipError_t launch_vw(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
-  constexpr int kMaxNW = VW >= 512 ? 2 : 8;
+  constexpr int kMaxNW = VW >= 2048 ? 1 : (VW >= 512 ? 2 : 8);
   // default: 4 wavefronts per group where the pairs are gathered
   // cooperatively (measured best at q = 6), else as many as fit
   const int nw = cfg.waves > 0 ? cfg.waves : (VW >= 32 && VW < 512 && cfg.coop ? 4 : kMaxNW);
@@ -341,6 +345,7 @@ hipError_t launch_scan_candidates(const CandArgs& a, const CandConfig& cfg, hipS
     case 32: return launch_vw<32>(a, cfg, s);
     case 128: return launch_vw<128>(a, cfg, s);
     case 512: return launch_vw<512>(a, cfg, s);
+    case 2048: return launch_vw<2048>(a, cfg, s);
     default: return hipErrorInvalidValue;
   }
 }

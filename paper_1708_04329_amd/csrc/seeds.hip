@@ -61,6 +61,7 @@ struct grim_seeds {
   uint8_t* staging = nullptr;     // host-resident reads copied in
   uint64_t staging_cap = 0;
   uint64_t* total_host = nullptr; // pinned [4]
+  uint32_t* bad = nullptr;        // device word: a read's offsets were rejected
 };
 
 namespace grim {
@@ -197,12 +198,21 @@ struct CandArgs2 {
   int32_t* cand_bin;
 };
 
+// A read whose offsets are out of order or outside [0, n_bases] gets no hits
+// and sets *bad; the call then fails before any later pass reads its bases.
 __global__ __launch_bounds__(256) void k_seed_hits(const uint64_t* start, uint32_t k, const uint8_t* bases,
-                                                   const int64_t* offsets, uint64_t n, uint64_t* hits) {
+                                                   uint64_t n_bases, const int64_t* offsets, uint64_t n,
+                                                   uint64_t* hits, uint32_t* bad) {
   const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  const uint8_t* rd = bases + offsets[r];
-  const int64_t L = offsets[r + 1] - offsets[r];
+  const int64_t o0 = offsets[r], o1 = offsets[r + 1];
+  if (o0 < 0 || o1 < o0 || (uint64_t)o1 > n_bases) {
+    hits[r] = 0;
+    atomicOr(bad, 1u);
+    return;
+  }
+  const uint8_t* rd = bases + o0;
+  const int64_t L = o1 - o0;
   uint64_t h = 0;
   for (int64_t o = 0; o + (int64_t)k <= L; o += k) {
     const int64_t c = seed_code(rd + o, k);
@@ -415,7 +425,7 @@ void free_seeds(grim_seeds* sd) {
   SeedGuard g(sd->device);
   for (void* p : {(void*)sd->start, (void*)sd->pos, (void*)sd->hits, (void*)sd->seg, (void*)sd->cnt,
                   (void*)sd->nruns, (void*)sd->outoff, (void*)sd->keys_a, (void*)sd->keys_b, (void*)sd->runs, sd->tmp,
-                  (void*)sd->staging})
+                  (void*)sd->staging, (void*)sd->bad})
     if (p) (void)hipFree(p);
   if (sd->hits_host) (void)hipHostFree(sd->hits_host);
   if (sd->total_host) (void)hipHostFree(sd->total_host);
@@ -567,11 +577,16 @@ int grim_seed_candidates(const grim_seeds* csd, const grim_reads* rd, uint32_t b
     GRIM_HIP_TRY(hipHostMalloc(&sd->hits_host, sd->hits_cap * sizeof(uint64_t), hipHostMallocDefault));
     sd->hits_host_cap = sd->hits_cap;
   }
-  hipLaunchKernelGGL(k_seed_hits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, sd->start, sd->k, bases, offsets,
-                     n, sd->hits);
+  if (!sd->bad) GRIM_HIP_TRY(hipMalloc(&sd->bad, sizeof(uint32_t)));
+  GRIM_HIP_TRY(launch_zero_words(sd->bad, 1, s));
+  hipLaunchKernelGGL(k_seed_hits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, sd->start, sd->k, bases,
+                     rd->n_bases, offsets, n, sd->hits, sd->bad);
   GRIM_HIP_TRY(hipGetLastError());
   GRIM_HIP_TRY(hipMemcpyAsync(sd->hits_host, sd->hits, n * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  uint32_t* bad_host = reinterpret_cast<uint32_t*>(sd->total_host + 3);
+  GRIM_HIP_TRY(hipMemcpyAsync(bad_host, sd->bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   GRIM_HIP_TRY(hipStreamSynchronize(s));
+  if (*bad_host) return set_error(GRIM_EINVAL, "read offsets out of order or outside [0, n_bases]");
   const uint64_t* H = sd->hits_host;
   // largest bin index: max(p - o, 0) / B < G / B
   const uint64_t max_bin = sd->G / bin_size;

@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstdlib>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -183,6 +184,11 @@ struct grim_server {
   grim::Clock::time_point t_first_submit, t_last_done;
   int device = 0;
   std::string fatal;  // a HIP failure that stopped the scheduler
+  // test hook, read at creation from GRIM_SERVE_TEST_FAIL_LAUNCH: launch
+  // number n >= 1 and every later one report a launch failure from the host
+  // without launching anything (0: off), so the failure path can be tested
+  // without a device fault
+  uint64_t fail_launch_at = 0;
 };
 
 namespace grim {
@@ -279,6 +285,7 @@ hipError_t start_prep(grim_server* S, Request& r) {
 // Launch one batch of segments on a free slot. Caller holds mu.
 hipError_t start_launch(grim_server* S, LaunchSlot& L, std::vector<serve::Segment>&& segs) {
   const grim_index* idx = S->idx;
+  if (S->fail_launch_at && S->launches + 1 >= S->fail_launch_at) return hipErrorLaunchFailure;
   SegTable t{};
   uint32_t total = 0;
   for (auto& sg : segs) {
@@ -329,8 +336,18 @@ void scheduler(grim_server* S) {
   std::unique_lock<std::mutex> lk(S->mu);
   while (true) {
     bool progress = false;
+    // 0. after a device failure nothing more is admitted: queued requests fail
+    if (!S->fatal.empty()) {
+      while (!S->queue.empty()) {
+        auto qit = S->reqs.find(S->queue.front());
+        S->queue.pop_front();
+        if (qit != S->reqs.end() && qit->second->state == RState::Queued)
+          finish(S, *qit->second, RState::Failed, GRIM_EDEVICE);
+        progress = true;
+      }
+    }
     // 1. admission, in arrival order
-    while (!S->queue.empty() && S->admitted < S->cfg.max_inflight && !S->status_free.empty()) {
+    while (S->fatal.empty() && !S->queue.empty() && S->admitted < S->cfg.max_inflight && !S->status_free.empty()) {
       auto qit = S->reqs.find(S->queue.front());
       if (qit == S->reqs.end() || qit->second->state != RState::Queued) {  // cancelled (and released) while queued
         S->queue.pop_front();
@@ -371,20 +388,26 @@ void scheduler(grim_server* S) {
     // 2. prepared requests join the batch former (or fail on bad reads)
     for (size_t i = 0; i < S->prepping.size();) {
       Request& r = *S->reqs[S->prepping[i]];
-      if (hipEventQuery(r.ready) != hipSuccess) {
+      const hipError_t q = hipEventQuery(r.ready);
+      if (q == hipErrorNotReady) {
         ++i;
         continue;
       }
+      if (q != hipSuccess && S->fatal.empty()) S->fatal = hipGetErrorString(q);
       S->prepping.erase(S->prepping.begin() + (long)i);
       progress = true;
       if (r.host_held) {
         S->host_arena.release(r.host_off);
         r.host_held = false;
       }
-      const uint32_t st = *r.status_host;
+      const uint32_t st = q == hipSuccess ? *r.status_host : 0u;
       if (r.cancel_requested) {
         S->admitted--;
         finish(S, r, RState::Canceled, GRIM_ECANCELED);
+      } else if (!S->fatal.empty()) {
+        // the server stopped while this request was prepared
+        S->admitted--;
+        finish(S, r, RState::Failed, GRIM_EDEVICE);
       } else if (st != 0) {
         S->admitted--;
         finish(S, r, RState::Failed, status_to_error(st));
@@ -429,9 +452,16 @@ void scheduler(grim_server* S) {
     }
     // 4. completions
     for (auto& L : S->slots) {
-      if (!L.busy || hipEventQuery(L.done) != hipSuccess) continue;
+      if (!L.busy) continue;
+      const hipError_t q = hipEventQuery(L.done);
+      if (q == hipErrorNotReady) continue;
       L.busy = false;
       progress = true;
+      if (q != hipSuccess) {
+        // the launch failed on the device: its requests fail and serving stops
+        if (S->fatal.empty()) S->fatal = hipGetErrorString(q);
+        for (auto& sg : L.segs) S->reqs[sg.req]->status = GRIM_EDEVICE;
+      }
       for (auto& sg : L.segs) {
         Request& r = *S->reqs[sg.req];
         r.done_reads += sg.count;
@@ -445,9 +475,24 @@ void scheduler(grim_server* S) {
       }
       L.segs.clear();
     }
+    if (!S->fatal.empty() && !S->former.empty()) {
+      // requests waiting for a launch that will not come
+      for (auto& kv : S->reqs) {
+        Request& r = *kv.second;
+        if (r.state != RState::Active) continue;
+        r.cancel_requested = true;
+        r.status = GRIM_EDEVICE;
+        S->former.remove(r.ticket);
+        if (r.launches_in_flight == 0) {
+          S->admitted--;
+          finish(S, r, RState::Failed, GRIM_EDEVICE);
+        }
+      }
+      progress = true;
+    }
     const bool busy = std::any_of(S->slots.begin(), S->slots.end(), [](const LaunchSlot& L) { return L.busy; });
     const bool idle = S->queue.empty() && S->prepping.empty() && S->former.empty() && !busy;
-    if (S->stop && (idle || (!S->fatal.empty() && S->prepping.empty() && !busy))) break;
+    if (S->stop && (idle || (!S->fatal.empty() && S->queue.empty() && S->prepping.empty() && !busy))) break;
     if (!progress) {
       if (idle) S->cv_work.wait_for(lk, std::chrono::milliseconds(5));
       else S->cv_work.wait_for(lk, std::chrono::microseconds(20));
@@ -522,6 +567,7 @@ extern "C" int grim_serve_create(const grim_index* idx, const grim_serve_config*
     c.arena_bytes = (fr - c.reserve_bytes) / 4096 * 4096;
   }
   S->cfg = c;
+  if (const char* t = std::getenv("GRIM_SERVE_TEST_FAIL_LAUNCH")) S->fail_launch_at = std::strtoull(t, nullptr, 10);
   hipError_t e;
   if ((e = hipMalloc(&S->dev_base, c.arena_bytes))) return fail(GRIM_ENOMEM, "device arena", e);
   S->dev_arena = serve::Arena(c.arena_bytes);
@@ -555,12 +601,12 @@ extern "C" int grim_serve_create(const grim_index* idx, const grim_serve_config*
 extern "C" int grim_serve_submit(grim_server* S, const grim_reads* rd, uint64_t* ticket) {
   clear_error();
   if (!S || !rd || !ticket) return set_error(GRIM_EINVAL, "NULL argument");
-  if (rd->on_device) return set_error(GRIM_EINVAL, "served reads must be host memory (on_device = 0)");
+  if (rd->on_device > 1) return set_error(GRIM_EINVAL, "reads.on_device must be 0 or 1");
   if (rd->n_reads == 0) return set_error(GRIM_EINVAL, "empty request");
   if (rd->n_reads > S->cfg.max_request_reads) return set_error(GRIM_EINVAL, "request larger than max_request_reads");
   if (!rd->offsets || (rd->n_bases && !rd->bases)) return set_error(GRIM_EINVAL, "NULL read arrays");
   if (rd->flags) return set_error(GRIM_EINVAL, "per-request flags are set in the server config");
-  if (rd->offsets[0] != 0 || (uint64_t)rd->offsets[rd->n_reads] != rd->n_bases)
+  if (!rd->on_device && (rd->offsets[0] != 0 || (uint64_t)rd->offsets[rd->n_reads] != rd->n_bases))
     return set_error(GRIM_EINVAL, "offsets must run from 0 to n_bases");
   auto r = std::make_unique<Request>();
   r->n_reads = rd->n_reads;
@@ -570,26 +616,53 @@ extern "C" int grim_serve_submit(grim_server* S, const grim_reads* rd, uint64_t*
   r->fp = serve::footprint(rd->n_reads, rd->n_bases, r->edits_kind != 0, S->idx->W,
                            token_capacity(rd->n_bases, rd->n_reads), sizeof(ReadDesc));
   const uint64_t host_bytes = r->fp.off_edits + (r->edits_kind ? serve::up256(rd->n_reads * 2) : 0);
-  std::lock_guard<std::mutex> lk(S->mu);
-  if (S->stop) return set_error(GRIM_ECANCELED, "server is shutting down");
-  if (S->dev_arena.aligned(r->fp.total) > S->dev_arena.capacity()) {
-    S->n_rejected++;
-    return set_error(GRIM_ENOMEM, "request needs %llu device bytes, more than the server's arena (%llu)",
-                     (unsigned long long)r->fp.total, (unsigned long long)S->dev_arena.capacity());
+  const uint16_t* edits = r->edits_kind == 1 ? rd->max_edits : rd->err_permille;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return set_error(GRIM_ECANCELED, "server is shutting down");
+    if (S->dev_arena.aligned(r->fp.total) > S->dev_arena.capacity()) {
+      S->n_rejected++;
+      return set_error(GRIM_ENOMEM, "request needs %llu device bytes, more than the server's arena (%llu)",
+                       (unsigned long long)r->fp.total, (unsigned long long)S->dev_arena.capacity());
+    }
+    if (host_bytes > S->host_arena.capacity()) {
+      S->n_rejected++;
+      return set_error(GRIM_ENOMEM, "request larger than the host staging arena");
+    }
+    if (!S->fatal.empty()) return set_error(GRIM_EDEVICE, "server stopped: %s", S->fatal.c_str());
+    if (!S->host_arena.alloc(host_bytes, &r->host_off))
+      return set_error(GRIM_EAGAIN, "host staging is full; retry when requests complete");
+    r->host_held = true;
   }
-  if (host_bytes > S->host_arena.capacity()) {
-    S->n_rejected++;
-    return set_error(GRIM_ENOMEM, "request larger than the host staging arena");
-  }
-  if (!S->fatal.empty()) return set_error(GRIM_EDEVICE, "server stopped: %s", S->fatal.c_str());
-  if (!S->host_arena.alloc(host_bytes, &r->host_off))
-    return set_error(GRIM_EAGAIN, "host staging is full; retry when requests complete");
-  r->host_held = true;
+  // the request's host block is held; copy the reads in without the lock
   uint8_t* h = S->host_base + r->host_off;
-  std::memcpy(h + r->fp.off_bases, rd->bases, rd->n_bases);
-  std::memcpy(h + r->fp.off_offsets, rd->offsets, (rd->n_reads + 1) * 8);
-  if (r->edits_kind == 1) std::memcpy(h + r->fp.off_edits, rd->max_edits, rd->n_reads * 2);
-  if (r->edits_kind == 2) std::memcpy(h + r->fp.off_edits, rd->err_permille, rd->n_reads * 2);
+  int rc = GRIM_OK;
+  if (!rd->on_device) {
+    std::memcpy(h + r->fp.off_bases, rd->bases, rd->n_bases);
+    std::memcpy(h + r->fp.off_offsets, rd->offsets, (rd->n_reads + 1) * 8);
+    if (r->edits_kind) std::memcpy(h + r->fp.off_edits, edits, rd->n_reads * 2);
+  } else {
+    // device reads: synchronous copies into the pinned block (the caller's
+    // arrays must be ready on the device; they are not used after the call)
+    DeviceGuard dg(S->device);
+    hipError_t e = hipMemcpy(h + r->fp.off_offsets, rd->offsets, (rd->n_reads + 1) * 8, hipMemcpyDeviceToHost);
+    const int64_t* offs = reinterpret_cast<const int64_t*>(h + r->fp.off_offsets);
+    if (e == hipSuccess && (offs[0] != 0 || (uint64_t)offs[rd->n_reads] != rd->n_bases)) {
+      rc = set_error(GRIM_EINVAL, "offsets must run from 0 to n_bases");
+    } else {
+      if (e == hipSuccess && rd->n_bases)
+        e = hipMemcpy(h + r->fp.off_bases, rd->bases, rd->n_bases, hipMemcpyDeviceToHost);
+      if (e == hipSuccess && r->edits_kind)
+        e = hipMemcpy(h + r->fp.off_edits, edits, rd->n_reads * 2, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) rc = set_error(GRIM_EDEVICE, "copy of device reads failed: %s", hipGetErrorString(e));
+    }
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (rc == GRIM_OK && S->stop) rc = set_error(GRIM_ECANCELED, "server is shutting down");
+  if (rc != GRIM_OK) {
+    S->host_arena.release(r->host_off);
+    return rc;
+  }
   r->ticket = S->next_ticket++;
   r->t_submit = Clock::now();
   if (!S->have_first) {

@@ -171,6 +171,7 @@ hipError_t launch_tokenize(const TokArgs& a, hipStream_t s) {
     case 5: hipLaunchKernelGGL(k_tokenize<5>, grid, block, 0, s, a); break;
     case 6: hipLaunchKernelGGL(k_tokenize<6>, grid, block, 0, s, a); break;
     case 7: hipLaunchKernelGGL(k_tokenize<7>, grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL(k_tokenize<8>, grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

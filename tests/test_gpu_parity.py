@@ -380,3 +380,69 @@ def test_save_load_roundtrip(tmp_path):
     with pytest.raises(grim.GrimError) as e:
         grim.grim_index_load(bad)
     assert e.value.code == grim.GRIM_EIO
+
+
+# ---------------------------------------------------------------------------
+# q = 8: the largest token length the boundary takes (4^8-bit, 8 KB vectors)
+# ---------------------------------------------------------------------------
+
+def test_q8_bin_major_bits_and_token_major_rejected(oracle):
+    rng = random.Random(808)
+    G, B, O, q = 30000, 97, 150, 8
+    ref = rand_ref(rng, G)
+    idx = build(ref, B, O, q, grim.LAYOUT_BM | grim.LAYOUT_REF)
+    inf = idx.info()
+    want = oracle.bits(ref, B, O, q)
+    nb, R4 = want.shape
+    assert R4 == 65536 and inf["bm_vec_words"] == 2048 and inf["bits_bytes"] == oracle.index_bytes(nb, q)
+    assert np.array_equal(bm_to_bits(idx.read(grim.LAYOUT_BM), R4, inf["bm_vec_words"], nb), want)
+    for layout in (grim.LAYOUT_TM, grim.LAYOUT_TM | grim.LAYOUT_BM):
+        with pytest.raises(grim.GrimError) as e:
+            build(ref, B, O, q, layout)
+        assert e.value.code == grim.GRIM_EINVAL
+    with pytest.raises(grim.GrimError) as e:
+        build(ref, B, O, 9, grim.LAYOUT_BM)
+    assert e.value.code == grim.GRIM_EINVAL
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_q8_candidates_match_oracle(oracle, persistent, monkeypatch):
+    """Candidate counts at q = 8, including reads whose tokens repeat 16 times or
+    more (homopolymers and short periods: more than four multiplicity planes)."""
+    import torch
+    monkeypatch.setenv("GRIM_CAND_PERSISTENT", str(persistent))
+    rng = random.Random(880 + persistent)
+    G, B, O, q = 40000, 113, 300, 8
+    ref = rand_ref(rng, G)
+    ref[5000:5400] = ord("A")
+    ref[9000:9400] = np.frombuffer(b"ACGTTG" * 66 + b"ACGT", np.uint8)
+    idx = build(ref, B, O, q, grim.LAYOUT_BM)
+    nb = idx.info()["n_bins"]
+    rd = rand_reads(rng, ref, 150, q, 300)
+    extra = [b"A" * 300, b"ACGTTG" * 50, b"A" * 8, ref[5100:5350].tobytes(), ref[9010:9290].tobytes()]
+    strs = [rd.bases[rd.offsets[r]:rd.offsets[r + 1]].tobytes() for r in range(rd.n)] + extra
+    rd = synth.reads_from_strings(strs)
+    co, cb = [0], []
+    for r in range(rd.n):
+        if r >= rd.n - len(extra):
+            sel = sorted(set(rng.sample(range(nb), 40)) | set(range(40, 50)) | set(range(77, 85)))
+        else:
+            sel = sorted(rng.sample(range(nb), rng.choice([0, 1, 5, 64, 130])))
+        cb += sel
+        co.append(len(cb))
+    co = np.array(co, np.int64)
+    cb = np.array(cb, np.int32)
+    err = np.array([rng.choice([0, 20, 50]) for _ in range(rd.n)], np.uint16)
+    log("cand q 8 persistent", persistent, "pairs", len(cb))
+    cnt = empty((len(cb),), torch.uint16)
+    pas = empty((len(cb),), torch.uint8)
+    rs = grim.ReadSet(dev(rd.bases), dev(rd.offsets), err_permille=dev(err), allow_short_overlap=True)
+    grim.grim_filter_candidates(idx, rs, dev(co), dev(cb), cnt, pas)
+    torch.cuda.synchronize()
+    bits = oracle.bits(ref, B, O, q)
+    wc, wp = oracle.scan_candidates(bits, q, rd.bases, rd.offsets, co, cb, err_pm_per_read=err)
+    got = host(cnt)
+    assert np.array_equal(got, wc)
+    assert np.array_equal(host(pas), wp)
+    # the homopolymer read meets 293 copies of its one token in the A run's bins
+    assert got.max() == 293

@@ -188,3 +188,26 @@ def test_seed_errors():
     # still usable
     n = grim.grim_seed_candidates(seeds, grim.ReadSet(dev(rd.bases), dev(rd.offsets)), 1000, 8, co, cb)
     assert n >= 1 and 0 in host(cb)[:n].tolist()
+
+
+@pytest.mark.parametrize("on_device", [True, False])
+def test_seed_rejects_bad_offsets(on_device):
+    """Offsets out of order, negative, or past n_bases fail the call with
+    GRIM_EINVAL (the bases of such a read are never read); the table stays usable."""
+    import torch
+    ref = rand_genome(random.Random(3), 5000)
+    seeds = grim.grim_seeds_build(dev(ref), 8)
+    bases = np.frombuffer(ref[100:400].tobytes(), np.uint8).copy()
+    conv = dev if on_device else (lambda a: np.ascontiguousarray(a))
+    co = empty((4,), torch.int64)
+    cb = empty((3 * 8,), torch.int32)
+    for offs in ([0, 100, 50, 300], [0, 100, 200, 301], [-5, 100, 200, 300], [0, 100, 200, 1 << 40]):
+        log("bad offsets", offs, "on_device", on_device)
+        with pytest.raises(grim.GrimError) as e:
+            grim.grim_seed_candidates(seeds, grim.ReadSet(conv(bases), conv(np.array(offs, np.int64))), 1000, 8,
+                                      co, cb)
+        assert e.value.code == grim.GRIM_EINVAL
+    n = grim.grim_seed_candidates(seeds, grim.ReadSet(conv(bases), conv(np.array([0, 100, 200, 300], np.int64))),
+                                  1000, 8, co, cb)
+    torch.cuda.synchronize()
+    assert n >= 1 and host(co)[-1] == n

@@ -183,3 +183,72 @@ def test_poll_and_timeout_paths(world):
         srv.poll(t + 999)
     srv.release(t)
     srv.destroy()
+
+
+def test_device_reads_equal_host_reads(world):
+    """A request whose reads are in device memory is copied at submit and served
+    to the same masks as the same reads given in host memory."""
+    import torch
+    w, ref, rd, idx = world
+    W = idx.info()["mask_words"]
+    reqs = make_requests(rd, [1, 300, 2500], seed=21)
+    srv = grim.Server(idx, grim.SERVE_CONTINUOUS, arena_bytes=1 << 30)
+    for sub in reqs:
+        d_bases, d_offs, d_e = dev(sub.bases), dev(sub.offsets), dev(sub.err_pm.astype(np.uint16))
+        torch.cuda.synchronize()
+        t = srv.submit(grim.ReadSet(d_bases, d_offs, err_permille=d_e))
+        d_bases.fill_(ord("N"))    # the server holds its own copy after submit
+        torch.cuda.synchronize()
+        res = srv.wait(t, 60000)
+        assert res["status"] == grim.GRIM_OK
+        got = d2h(res["mask"], sub.n * W * 4).view(np.uint32).reshape(sub.n, W)
+        assert np.array_equal(got, alone(idx, sub)), sub.n
+        srv.release(t)
+    # device offsets that do not run from 0 to n_bases are rejected at submit
+    sub = reqs[1]
+    bad = sub.offsets.copy()
+    bad[-1] += 1
+    with pytest.raises(grim.GrimError) as e:
+        srv.submit(grim.ReadSet(dev(sub.bases), dev(bad), err_permille=dev(sub.err_pm.astype(np.uint16))))
+    assert e.value.code == grim.GRIM_EINVAL
+    srv.destroy()
+
+
+def test_launch_failure_ends_every_request(world, monkeypatch):
+    """After a launch fails (forced from the host: the third launch reports a
+    failure without launching), every request ends: those whose launches ran
+    keep their masks, the rest fail with GRIM_EDEVICE; later submits are refused
+    and the server shuts down without hanging."""
+    w, ref, rd, idx = world
+    W = idx.info()["mask_words"]
+    monkeypatch.setenv("GRIM_SERVE_TEST_FAIL_LAUNCH", "3")
+    srv = grim.Server(idx, grim.SERVE_CONTINUOUS, max_batch_reads=1000, slice_reads=500, n_streams=1,
+                      max_inflight=4, arena_bytes=1 << 30)
+    monkeypatch.delenv("GRIM_SERVE_TEST_FAIL_LAUNCH")
+    reqs = make_requests(rd, [400, 900, 2000, 3000, 50, 700, 10, 2500], seed=31)
+    tickets = []
+    for s in reqs:
+        try:
+            tickets.append(srv.submit(rs_host(s)))
+        except grim.GrimError as e:     # refused once the server has stopped
+            assert e.code == grim.GRIM_EDEVICE
+            tickets.append(None)
+    statuses = []
+    for t, sub in zip(tickets, reqs):
+        if t is None:
+            statuses.append(grim.GRIM_EDEVICE)
+            continue
+        res = srv.wait(t, 60000)
+        statuses.append(res["status"])
+        assert res["status"] in (grim.GRIM_OK, grim.GRIM_EDEVICE), res
+        if res["status"] == grim.GRIM_OK:
+            got = d2h(res["mask"], sub.n * W * 4).view(np.uint32).reshape(sub.n, W)
+            assert np.array_equal(got, alone(idx, sub))
+    log("statuses after the forced failure", statuses)
+    assert statuses[0] == grim.GRIM_OK and statuses.count(grim.GRIM_EDEVICE) >= 1
+    with pytest.raises(grim.GrimError) as e:
+        srv.submit(rs_host(reqs[0]))
+    assert e.value.code == grim.GRIM_EDEVICE
+    st = srv.stats()
+    assert st["completed"] + st["failed"] == sum(t is not None for t in tickets)
+    srv.destroy()
