@@ -185,6 +185,28 @@ int grim_filter_candidates(const grim_index* idx, const grim_reads* reads,
                            const int64_t* cand_off, const int32_t* cand_bin, uint64_t n_cand,
                            uint16_t* count_out, uint8_t* pass_out, void* hip_stream);
 
+/* grim_filter_candidates without any device allocation, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. Same arguments, results and errors as
+ * grim_filter_candidates, with two differences:
+ *   - the reads must be in device memory (on_device = 1);
+ *   - the call's scratch (status words, per-read thresholds, token lists) is
+ *     a fixed device array of GRIM_STATIC_SCRATCH_BYTES that each GPU the
+ *     library runs on holds until the process ends; a call needs
+ *     256 + (n_reads + 1) * 4 (rounded up to 256) + 4 * (n_bases + 64 *
+ *     n_reads + 128) bytes of it, about 10 MB per 100K reads of 100 bases;
+ *     larger calls fail with GRIM_EINVAL (split them, or use
+ *     grim_filter_candidates).
+ * Every call on one GPU shares that GPU's array. The library runs such calls
+ * one at a time per GPU within a process, and a call returns only after its
+ * work on hip_stream is complete, so calls cannot overlap; the array keeps
+ * the last call's contents, and each call clears what must start at zero.
+ * The launch shape is the index's (defaults or grim_tune's choice). */
+#define GRIM_STATIC_SCRATCH_BYTES (64ull << 20)
+int grim_filter_candidates_static(const grim_index* idx, const grim_reads* reads, const int64_t* cand_off,
+                                  const int32_t* cand_bin, uint64_t n_cand, uint16_t* count_out,
+                                  uint8_t* pass_out, void* hip_stream);
+
 /* Verification of listed (read, bin) pairs, the step after the filter: a
  * location that passes is aligned with dynamic programming (Section 1,
  * seed-and-extend step 5), and a passing location that yields no mapping

@@ -22,7 +22,7 @@ OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgrim.so")
 
 SOURCES = ["api.hip", "batch.hip", "serve.hip", "tokenize.hip", "build_index.hip", "scan_allbins.hip", "scan_candidates.hip",
-           "order.hip", "verify.hip", "seeds.hip", "summary.hip"]
+           "order.hip", "verify.hip", "seeds.hip", "summary.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -139,7 +139,8 @@ EXPORTS = ["grim_abi_version", "grim_last_error", "grim_build_index", "grim_inde
            "grim_serve_submit", "grim_serve_poll", "grim_serve_wait", "grim_serve_release", "grim_serve_cancel",
            "grim_serve_stats", "grim_serve_reset_stats", "grim_serve_destroy", "grim_verify_candidates",
            "grim_seeds_build", "grim_seeds_info", "grim_seeds_free", "grim_seed_candidates",
-           "grim_reverse_complement", "grim_mask_summary", "grim_verify_candidates_bounded"]
+           "grim_reverse_complement", "grim_mask_summary", "grim_verify_candidates_bounded",
+           "grim_filter_candidates_static"]
 
 _lib = None
 
@@ -165,6 +166,7 @@ def lib(path: str = LIB_PATH):
         "grim_index_free": ([P], None),
         "grim_filter_scan": ([P, ctypes.POINTER(_Reads), P, P, U32, P], I),
         "grim_filter_candidates": ([P, ctypes.POINTER(_Reads), P, P, U64, P, P, P], I),
+        "grim_filter_candidates_static": ([P, ctypes.POINTER(_Reads), P, P, U64, P, P, P], I),
         "grim_verify_candidates": ([P, ctypes.POINTER(_Reads), P, P, U64, P, P, P, P], I),
         "grim_verify_candidates_bounded": ([P, ctypes.POINTER(_Reads), P, P, U64, P, P, P, P], I),
         "grim_seeds_build": ([P, U64, U32, U32, P, PP], I),
@@ -461,6 +463,23 @@ def grim_filter_candidates(index: Index, reads: ReadSet, cand_off, cand_bin, cou
     _check(lib().grim_filter_candidates(index.handle, ctypes.byref(r), _ptr(cand_off), _ptr(cand_bin),
                                         len(cand_bin), _ptr(count_out), _ptr(pass_out),
                                         _stream_handle(stream)))
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def grim_filter_candidates_static(index: Index, reads: ReadSet, cand_off, cand_bin, count_out=None, pass_out=None,
+                                  stream=None):
+    """grim_filter_candidates with no device allocation (fixed per-GPU scratch of
+    STATIC_SCRATCH_BYTES); the reads must be device tensors."""
+    _check_dtype(cand_off, "cand_off", np.int64)
+    _check_dtype(cand_bin, "cand_bin", np.int32)
+    _check_dtype(count_out, "count_out", np.uint16)
+    _check_dtype(pass_out, "pass_out", np.uint8)
+    r = reads._struct()
+    _check(lib().grim_filter_candidates_static(index.handle, ctypes.byref(r), _ptr(cand_off), _ptr(cand_bin),
+                                               len(cand_bin), _ptr(count_out), _ptr(pass_out),
+                                               _stream_handle(stream)))
 
 
 def grim_verify_candidates(index: Index, reads: ReadSet, cand_off, cand_bin, verify_mask=None, dist_out=None,
