@@ -37,7 +37,7 @@ __device__ __forceinline__ uint32_t base_code(uint32_t b, bool* ok) {
 // bases come in with three 16-byte loads when the reference is 16-byte
 // aligned (bases at or past G read as invalid). For every valid token it
 // calls emit(code, x, rem) with x = s / B and rem = s % B, both tracked
-// incrementally from one division per run.
+// incrementally from one division per run (x < 2^31: at most 2^31 bins).
 template <int Q, typename Emit>
 __device__ __forceinline__ void for_tokens(const uint8_t* ref, uint64_t G, bool aligned, uint64_t lo, uint64_t hi,
                                            uint32_t B, Emit emit) {
@@ -66,8 +66,12 @@ __device__ __forceinline__ void for_tokens(const uint8_t* ref, uint64_t G, bool 
         w[k] = word;
       }
     }
-    uint64_t x = s0 / B;
-    uint32_t rem = (uint32_t)(s0 - x * B);
+    // starts s0 + u with u in [u_lo, u_hi) lie in [lo, hi)
+    const int u_lo = s0 < lo ? (int)(lo - s0) : 0;
+    const int u_hi = hi - s0 < (uint64_t)kRun ? (int)(hi - s0) : kRun;
+    const uint64_t x64 = s0 / B;
+    uint32_t x = (uint32_t)x64;
+    uint32_t rem = (uint32_t)(s0 - x64 * B);
     uint32_t code = 0;
     int run = 0;  // valid bases ending at the current one
 #pragma unroll
@@ -77,8 +81,8 @@ __device__ __forceinline__ void for_tokens(const uint8_t* ref, uint64_t G, bool 
       run = ok ? run + 1 : 0;
       code = ((code << 2) | c) & MASK;
       if (i >= Q - 1) {
-        const uint64_t s = s0 + (uint64_t)(i - (Q - 1));  // start of the window ending here
-        if (run >= Q && s >= lo && s < hi) emit(code, x, rem);
+        const int u = i - (Q - 1);  // the window ending here starts at s0 + u
+        if (run >= Q && u >= u_lo && u < u_hi) emit(code, x, rem);
         if (++rem == B) {
           rem = 0;
           ++x;
@@ -88,25 +92,44 @@ __device__ __forceinline__ void for_tokens(const uint8_t* ref, uint64_t G, bool 
   }
 }
 
-// Calls f(bin) for every bin in [x0, xl] whose extent [b*B, b*B + B + O)
+// Calls f(bin - x0) for every bin in [x0, xl] whose extent [b*B, b*B + B + O)
 // holds token start s = x*B + rem: bins x, x - 1, ... while rem + j*B < B + O.
-template <typename F>
-__device__ __forceinline__ void for_bins(uint64_t x, uint32_t rem, uint32_t B, uint32_t O, uint64_t x0, uint64_t xl,
+// When O <= B (every workload here) that is bin x, and bin x - 1 when rem < O:
+// two predicated calls instead of a loop.
+template <bool SHORT_O, typename F>
+__device__ __forceinline__ void for_bins(uint32_t x, uint32_t rem, uint32_t B, uint32_t O, uint32_t x0, uint32_t xl,
                                          F f) {
+  if constexpr (SHORT_O) {
+    if (x >= x0 && x <= xl) f(x - x0);
+    if (rem < O && x > x0 && x - 1 <= xl) f(x - 1 - x0);
+    return;
+  }
   const uint64_t reach = (uint64_t)B + O;
   uint64_t off = rem;  // s - bin * B for bin = x - j
-  for (uint64_t j = 0; j <= x && off < reach; ++j, off += B) {
-    const uint64_t bin = x - j;
-    if (bin < x0) break;
-    if (bin <= xl) f(bin);
+  for (uint32_t bin = x;; --bin, off += B) {
+    if (off >= reach || bin < x0) break;
+    if (bin <= xl) f(bin - x0);
+    if (bin == 0) break;
   }
 }
 
-// Token-major tile: TW words = 32 * TW bins, every row of R4 = 4^Q tokens, in LDS.
-template <int Q>
+// Words of a token-major row a build tile covers: 64 KB of LDS per tile (two
+// workgroups of 1024 threads per CU), at most 32 words.
+constexpr int build_tile_words(int q) { return q <= 4 ? 32 : (16384 >> (2 * q - 4)) / 16; }
+static_assert(build_tile_words(5) == 16 && build_tile_words(6) == 4 && build_tile_words(7) == 1, "tile widths");
+
+// Token-major tile: TW words = 32 * TW bins of every row of R4 = 4^Q tokens,
+// in LDS word-major (word w of row t at w * R4 + (t ^ (w & SW))): the lanes of
+// a wavefront take starts 32 bases apart, so most of them set bits of the same
+// 32-bin word of random rows; with rows contiguous per word their atomics
+// spread over the banks instead of all hitting one. The XOR keeps the
+// row-major read-out (consecutive lanes: consecutive words of a row) off a
+// single bank as well.
+template <int Q, bool SHORT_O>
 __global__ __launch_bounds__(1024) void k_build_tm(BuildArgs a, bool aligned) {
-  constexpr int TW = Q <= 5 ? 32 : (Q == 6 ? 8 : 2);
+  constexpr int TW = build_tile_words(Q);
   constexpr uint32_t R4 = 1u << (2 * Q);
+  constexpr uint32_t SW = (R4 < 32 ? R4 : 32) - 1;
   __shared__ uint32_t tile[R4 * TW];
   const uint64_t w0 = (uint64_t)blockIdx.x * TW;  // first word of the tile
   const uint64_t x0 = w0 * 32;                     // first bin of the tile
@@ -119,10 +142,10 @@ __global__ __launch_bounds__(1024) void k_build_tm(BuildArgs a, bool aligned) {
     if (hi > last_start) hi = last_start;
     const uint64_t lo = x0 * a.B;
     if (lo < hi) {
-      for_tokens<Q>(a.ref, a.G, aligned, lo, hi, a.B, [&](uint32_t code, uint64_t x, uint32_t rem) {
-        for_bins(x, rem, a.B, a.O, x0, xl, [&](uint64_t bin) {
-          const uint32_t lx = (uint32_t)(bin - x0);
-          atomicOr(&tile[code * TW + (lx >> 5)], 1u << (lx & 31));
+      for_tokens<Q>(a.ref, a.G, aligned, lo, hi, a.B, [&](uint32_t code, uint32_t x, uint32_t rem) {
+        for_bins<SHORT_O>(x, rem, a.B, a.O, (uint32_t)x0, (uint32_t)xl, [&](uint32_t lx) {
+          const uint32_t w = lx >> 5;
+          atomicOr(&tile[w * R4 + (code ^ (w & SW))], 1u << (lx & 31));
         });
       });
     }
@@ -130,12 +153,12 @@ __global__ __launch_bounds__(1024) void k_build_tm(BuildArgs a, bool aligned) {
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < R4 * TW; i += blockDim.x) {
     const uint32_t row = i / TW, w = i % TW;
-    a.tm[(uint64_t)row * a.row_words + w0 + w] = tile[i];
+    a.tm[(uint64_t)row * a.row_words + w0 + w] = tile[w * R4 + (row ^ (w & SW))];
   }
 }
 
 // Bin-major: a workgroup builds kBins consecutive bin vectors of VW words.
-template <int Q>
+template <int Q, bool SHORT_O>
 __global__ __launch_bounds__(1024) void k_build_bm(BuildArgs a, bool aligned) {
   constexpr int VW = (1 << (2 * Q)) >= 32 ? (1 << (2 * Q)) / 32 : 1;
   constexpr int kBins = VW >= 512 ? 16 : 32;
@@ -149,9 +172,9 @@ __global__ __launch_bounds__(1024) void k_build_bm(BuildArgs a, bool aligned) {
   if (hi > last_start) hi = last_start;
   const uint64_t lo = x0 * a.B;
   if (lo < hi) {
-    for_tokens<Q>(a.ref, a.G, aligned, lo, hi, a.B, [&](uint32_t code, uint64_t x, uint32_t rem) {
-      for_bins(x, rem, a.B, a.O, x0, xl, [&](uint64_t bin) {
-        atomicOr(&vec[(uint32_t)(bin - x0) * VW + (code >> 5)], 1u << (code & 31));
+    for_tokens<Q>(a.ref, a.G, aligned, lo, hi, a.B, [&](uint32_t code, uint32_t x, uint32_t rem) {
+      for_bins<SHORT_O>(x, rem, a.B, a.O, (uint32_t)x0, (uint32_t)xl, [&](uint32_t lx) {
+        atomicOr(&vec[lx * VW + (code >> 5)], 1u << (code & 31));
       });
     });
   }
@@ -160,23 +183,34 @@ __global__ __launch_bounds__(1024) void k_build_bm(BuildArgs a, bool aligned) {
   for (uint32_t i = threadIdx.x; i < nbins * VW; i += blockDim.x) a.bm[x0 * VW + i] = vec[i];
 }
 
+template <int Q>
+void launch_tm_q(const BuildArgs& a, bool al, dim3 g, hipStream_t s) {
+  if (a.O <= a.B) hipLaunchKernelGGL((k_build_tm<Q, true>), g, dim3(1024), 0, s, a, al);
+  else hipLaunchKernelGGL((k_build_tm<Q, false>), g, dim3(1024), 0, s, a, al);
+}
+
+template <int Q>
+void launch_bm_q(const BuildArgs& a, bool al, dim3 g, hipStream_t s) {
+  if (a.O <= a.B) hipLaunchKernelGGL((k_build_bm<Q, true>), g, dim3(1024), 0, s, a, al);
+  else hipLaunchKernelGGL((k_build_bm<Q, false>), g, dim3(1024), 0, s, a, al);
+}
+
 }  // namespace
 
 hipError_t launch_build_tm(const BuildArgs& a, hipStream_t s) {
-  const int TW = tm_tile_words(a.q);
-  const uint64_t tiles = a.row_words / TW;
+  if (a.q < 1 || a.q > 7) return hipErrorInvalidValue;  // q = 8: a tile of 4^8 + 1 rows does not fit LDS
+  const uint64_t tiles = a.row_words / build_tile_words((int)a.q);
   if (tiles == 0) return hipSuccess;
   const bool al = (reinterpret_cast<uintptr_t>(a.ref) & 15u) == 0;
-  const dim3 g((unsigned)tiles), b(1024);
+  const dim3 g((unsigned)tiles);
   switch (a.q) {
-    case 1: hipLaunchKernelGGL(k_build_tm<1>, g, b, 0, s, a, al); break;
-    case 2: hipLaunchKernelGGL(k_build_tm<2>, g, b, 0, s, a, al); break;
-    case 3: hipLaunchKernelGGL(k_build_tm<3>, g, b, 0, s, a, al); break;
-    case 4: hipLaunchKernelGGL(k_build_tm<4>, g, b, 0, s, a, al); break;
-    case 5: hipLaunchKernelGGL(k_build_tm<5>, g, b, 0, s, a, al); break;
-    case 6: hipLaunchKernelGGL(k_build_tm<6>, g, b, 0, s, a, al); break;
-    case 7: hipLaunchKernelGGL(k_build_tm<7>, g, b, 0, s, a, al); break;
-    default: return hipErrorInvalidValue;  // q = 8: a tile of 4^8 + 1 rows does not fit LDS
+    case 1: launch_tm_q<1>(a, al, g, s); break;
+    case 2: launch_tm_q<2>(a, al, g, s); break;
+    case 3: launch_tm_q<3>(a, al, g, s); break;
+    case 4: launch_tm_q<4>(a, al, g, s); break;
+    case 5: launch_tm_q<5>(a, al, g, s); break;
+    case 6: launch_tm_q<6>(a, al, g, s); break;
+    default: launch_tm_q<7>(a, al, g, s); break;
   }
   return hipGetLastError();
 }
@@ -187,16 +221,16 @@ hipError_t launch_build_bm(const BuildArgs& a, hipStream_t s) {
   const uint64_t blocks = (a.nb + kBins - 1) / kBins;
   if (blocks == 0) return hipSuccess;
   const bool al = (reinterpret_cast<uintptr_t>(a.ref) & 15u) == 0;
-  const dim3 g((unsigned)blocks), b(1024);
+  const dim3 g((unsigned)blocks);
   switch (a.q) {
-    case 1: hipLaunchKernelGGL(k_build_bm<1>, g, b, 0, s, a, al); break;
-    case 2: hipLaunchKernelGGL(k_build_bm<2>, g, b, 0, s, a, al); break;
-    case 3: hipLaunchKernelGGL(k_build_bm<3>, g, b, 0, s, a, al); break;
-    case 4: hipLaunchKernelGGL(k_build_bm<4>, g, b, 0, s, a, al); break;
-    case 5: hipLaunchKernelGGL(k_build_bm<5>, g, b, 0, s, a, al); break;
-    case 6: hipLaunchKernelGGL(k_build_bm<6>, g, b, 0, s, a, al); break;
-    case 7: hipLaunchKernelGGL(k_build_bm<7>, g, b, 0, s, a, al); break;
-    case 8: hipLaunchKernelGGL(k_build_bm<8>, g, b, 0, s, a, al); break;
+    case 1: launch_bm_q<1>(a, al, g, s); break;
+    case 2: launch_bm_q<2>(a, al, g, s); break;
+    case 3: launch_bm_q<3>(a, al, g, s); break;
+    case 4: launch_bm_q<4>(a, al, g, s); break;
+    case 5: launch_bm_q<5>(a, al, g, s); break;
+    case 6: launch_bm_q<6>(a, al, g, s); break;
+    case 7: launch_bm_q<7>(a, al, g, s); break;
+    case 8: launch_bm_q<8>(a, al, g, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
