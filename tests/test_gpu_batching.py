@@ -1,6 +1,7 @@
 """Batching layer on the GPU: tuned and persistent launch shapes change no
-output bit, and the graph-captured batcher matches the eager calls on every
-replay (with eager work in between), for both slots and varying batch sizes."""
+output bit, and the graph-captured batcher matches the eager calls and the
+oracle on every replay (with eager work in between), for both slots and
+varying batch sizes."""
 
 from __future__ import annotations
 
@@ -145,9 +146,10 @@ def _fill_batch(buf, rd, ids, co=None, cb=None, edits=None):
     return sub, nb, npair
 
 
-def test_batcher_candidates_every_replay_matches_eager(uneven):
+def test_batcher_candidates_every_replay_matches_eager(uneven, oracle):
     w, ref, rd, co, cb, idx = uneven
     ep = rd.err_pm.astype(np.uint16)
+    bits = oracle.bits(ref, w.bin_size, w.overlap, w.q)
     grim.grim_index_set_config(idx, {"mode": grim.MODE_CANDIDATES, "cand_waves": 4, "cand_persistent": 1,
                                      "cand_groups_per_cu": 4, "cand_coop": 1})
     b = grim.Batcher(idx, grim.MODE_CANDIDATES, max_reads=2000, max_bases=2000 * 250, max_cand=2000 * 1024,
@@ -167,6 +169,9 @@ def test_batcher_candidates_every_replay_matches_eager(uneven):
             scb = np.concatenate([cb[co[i]:co[i + 1]] for i in ids]).astype(np.int32)
             want = run_cand(idx, sub, sco, scb, ep[ids])
             assert np.array_equal(got_c, want[0]) and np.array_equal(got_p, want[1]), it
+            # and the oracle on the same batch
+            oc, op = oracle.scan_candidates(bits, w.q, sub.bases, sub.offsets, sco, scb, err_pm_per_read=ep[ids])
+            assert np.array_equal(got_c, oc) and np.array_equal(got_p, op), it
         n = rng.choice([1, 17, 640, 2000])
         ids = np.sort(np.random.default_rng(it).choice(rd.n, size=n, replace=False))
         buf = b.buffers(slot)
@@ -179,13 +184,15 @@ def test_batcher_candidates_every_replay_matches_eager(uneven):
     b.free()
 
 
-def test_batcher_scan_every_replay_matches_eager():
+def test_batcher_scan_every_replay_matches_eager(oracle):
     import torch
     w = C.shrink(C.workload("c3"), genome_len=3_000_000, n_reads=3000)
     ref = synth.genome(w.genome)
     rd = synth.reads(w.reads, ref)
     idx = grim.grim_build_index(dev(ref), w.bin_size, w.overlap, w.q, grim.LAYOUT_TM)
     W = idx.info()["mask_words"]
+    nb = idx.info()["n_bins"]
+    bits = oracle.bits(ref, w.bin_size, w.overlap, w.q)
     b = grim.Batcher(idx, grim.MODE_SCAN, max_reads=1000, max_bases=1000 * 150, edits_kind=grim.BATCH_EDITS_NONE,
                      err_permille_all=45)
     for it in range(6):
@@ -200,6 +207,11 @@ def test_batcher_scan_every_replay_matches_eager():
         m = empty((n, W), torch.uint32)
         grim.grim_filter_scan(idx, grim.ReadSet(dev(sub.bases), dev(sub.offsets), err_permille_all=45), m)
         assert np.array_equal(got, host(m)), it
+        # every 7th row of the replay against the oracle
+        rows = np.arange(0, n, 7)
+        s7 = sub.subset(rows)
+        _, wp = oracle.scan_all(bits, w.q, s7.bases, s7.offsets, err_permille=45, want_counts=False)
+        assert np.array_equal(unpack_mask(got[rows], nb), wp), it
     b.free()
 
 
