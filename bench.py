@@ -293,8 +293,9 @@ def main():
                                       f"{info['bm_bytes'] / 1e6:.1f} MB index is cache-resident, so the gather "
                                       f"runs at {work_units / (avg_ms * 1e-3) / 1e9:.0f} GB/s from L2 and the "
                                       "Infinity Cache, not HBM"})
+    frac = roofline["frac"]
     log(f"{ms_per_step:.2f} ms/step, {value:.4g} checks/s; kernel {avg_ms:.2f} ms, "
-        f"roofline frac {roofline['frac']:.3f}")
+        f"roofline frac {'n/a' if frac is None else f'{frac:.3f}'}")
 
     out = {
         "metric": METRIC, "value": value, "unit": "checks/s", "n_gpus": 1, "steps": args.steps,

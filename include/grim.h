@@ -346,7 +346,8 @@ typedef struct {
                                   for calls of at least 2^20 reads, one wavefront per read below */
   uint32_t cand_groups_per_cu; /* candidates, persistent: workgroups per CU in the fixed grid */
   uint32_t cand_coop;          /* candidates, q >= 5: 1 = 4^q/512 lanes share a pair, each streaming
-                                  64 contiguous bytes of the bin vector; 0 = one lane per pair */
+                                  16-byte chunks of the bin vector; 0 = one lane per pair; 2 (q = 5)
+                                  = four reads per wavefront, 16 lanes each, 4 lanes per pair */
   uint32_t n_tried;            /* grim_tune: shapes timed */
   double best_ms;              /* grim_tune: kernel time of the chosen shape on the sample */
   double default_ms;           /* grim_tune: kernel time of the default shape on the sample */
@@ -356,9 +357,9 @@ typedef struct {
  * fastest on `idx` for later calls, unless it beats the default shape by less
  * than 5% on the sample (then the default stays; short samples are dominated
  * by launch overhead). The defaults: all-bins 1024 threads, 4096 reads per
- * chunk, 4 words per lane; candidates 4 wavefronts per workgroup, cooperative
- * lanes at q >= 5, and at q = 5 the persistent grid of 8 workgroups per CU
- * for calls of 2^20 reads or more (cand_persistent = 2).
+ * chunk, 4 words per lane; candidates at q = 5 four reads per wavefront
+ * (cand_coop = 2) in workgroups of 2 wavefronts, at q = 6 and 7 cooperative
+ * lanes in workgroups of 4 wavefronts, otherwise one lane per pair.
  * The choice is also kept in the file named by the
  * GRIM_TUNE_CACHE environment variable, keyed by mode, q and size class, for
  * later processes). Mode: candidates if cand_off is non-NULL (device arrays

@@ -263,7 +263,10 @@ CandConfig cand_config_from_env(CandConfig c) {
     c.persistent = v == 2 ? 2 : (v ? 1 : 0);
   }
   if (const char* t = std::getenv("GRIM_CAND_GROUPS_PER_CU")) c.groups_per_cu = std::atoi(t);
-  if (const char* t = std::getenv("GRIM_CAND_COOP")) c.coop = std::atoi(t) ? 1 : 0;
+  if (const char* t = std::getenv("GRIM_CAND_COOP")) {
+    const int v = std::atoi(t);
+    c.coop = v == 2 ? 2 : (v ? 1 : 0);
+  }
   if (c.waves < 0 || c.waves > 8) c.waves = 0;
   if (c.groups_per_cu < 1 || c.groups_per_cu > 64) c.groups_per_cu = 2;
   return c;
@@ -306,14 +309,7 @@ int fill_geometry(grim_index* idx, uint64_t G, uint32_t B, uint32_t O, uint32_t 
   idx->tm_bytes = (layout & GRIM_LAYOUT_TM) ? (uint64_t)idx->R4 * idx->row_words * 4 : 0;
   idx->bm_bytes = (layout & GRIM_LAYOUT_BM) ? idx->nb * idx->vec_words * 4 : 0;
   idx->ref_bytes = (layout & GRIM_LAYOUT_REF) ? G : 0;
-  if (idx->vec_words == 32) {
-    // q = 5 (128-byte vectors, short lists): for calls of a million reads or
-    // more, a persistent grid of 8 groups of 4 wavefronts per CU, measured 6%
-    // faster than one wavefront per read on 4M reads (wavefront launch, not
-    // the work, bounds the per-read grid there)
-    idx->cand_cfg.persistent = 2;
-    idx->cand_cfg.groups_per_cu = 8;
-  }
+  idx->cand_cfg = default_cand_config(idx->vec_words);
   return GRIM_OK;
 }
 

@@ -133,7 +133,7 @@ int apply_result(grim_index* idx, const grim_tune_result* r) {
     if (r->cand_persistent > 2) return set_error(GRIM_EINVAL, "cand_persistent must be 0, 1 or 2");
     if (r->cand_groups_per_cu < 1 || r->cand_groups_per_cu > 64)
       return set_error(GRIM_EINVAL, "cand_groups_per_cu must be in [1, 64]");
-    if (r->cand_coop > 1) return set_error(GRIM_EINVAL, "cand_coop must be 0 or 1");
+    if (r->cand_coop > 2) return set_error(GRIM_EINVAL, "cand_coop must be 0, 1 or 2");
     idx->cand_cfg.coop = (int)r->cand_coop;
     idx->cand_cfg.waves = (int)r->cand_waves;
     idx->cand_cfg.persistent = (int)r->cand_persistent;
@@ -293,8 +293,10 @@ extern "C" int grim_tune(grim_index* idx, const grim_reads* rd, const int64_t* c
     a.status = idx->ws.status;
     a.work = idx->ws.status + 4;
     const int waves[] = {1, 2, 4, 8};
-    const CandConfig dflt;
-    for (int coop = 0; coop <= (idx->vec_words >= 32 ? 1 : 0); ++coop)
+    const CandConfig dflt = default_cand_config(idx->vec_words);
+    // lane layouts: one lane per pair; groups of lanes per pair (q >= 5); four reads per wavefront (q = 5)
+    const int max_coop = idx->vec_words == 32 ? 2 : (idx->vec_words > 32 && idx->vec_words <= 512 ? 1 : 0);
+    for (int coop = 0; coop <= max_coop; ++coop)
       for (int nw : waves)
         for (int pers = 0; pers <= 1; ++pers)
           for (int gpc : {2, 4, 8, 16}) {
@@ -307,11 +309,9 @@ extern "C" int grim_tune(grim_index* idx, const grim_reads* rd, const int64_t* c
             const double ms = time_it([&] { return launch_scan_candidates(a, c, s); });
             if (ms < 0) continue;
             ++tried;
-            // the shape an untuned index uses (fill_geometry; at q = 5 the
-            // persistent grid 4 x 8 for calls of 2^20 reads or more)
-            const bool dpers = idx->vec_words == 32 && rd->n_reads >= kPersistentMinReads;
-            if (coop == (idx->vec_words >= 32 ? dflt.coop : 0) && nw == 4 && pers == (dpers ? 1 : 0) &&
-                gpc == (dpers ? 8 : 2))
+            // the shape an untuned index uses (default_cand_config)
+            if (coop == dflt.coop && (dflt.waves == 0 || nw == dflt.waves) && pers == dflt.persistent &&
+                gpc == dflt.groups_per_cu && (dflt.waves != 0 || nw == 8))
               default_ms = ms;
             if (ms < best.best_ms) {
               best.best_ms = ms;
@@ -324,12 +324,11 @@ extern "C" int grim_tune(grim_index* idx, const grim_reads* rd, const int64_t* c
     // a shape that beats the default by under 5% on the sample is noise more
     // often than not (short samples are dominated by launch overhead): keep the default
     if (default_ms > 0 && best.best_ms > 0.95 * default_ms) {
-      const bool q5 = idx->vec_words == 32;
       best.best_ms = default_ms;
-      best.cand_waves = 4;
-      best.cand_persistent = q5 ? 2u : 0u;
-      best.cand_groups_per_cu = q5 ? 8u : 2u;
-      best.cand_coop = idx->vec_words >= 32 ? (uint32_t)dflt.coop : 0u;
+      best.cand_waves = (uint32_t)dflt.waves;
+      best.cand_persistent = (uint32_t)dflt.persistent;
+      best.cand_groups_per_cu = (uint32_t)dflt.groups_per_cu;
+      best.cand_coop = (uint32_t)dflt.coop;
     }
     best.threads = (uint32_t)idx->scan_cfg.threads;
     best.reads_per_chunk = (uint32_t)idx->scan_cfg.reads_per_chunk;

@@ -231,9 +231,27 @@ struct CandConfig {
   int persistent = 0;    // 1: fixed grid, reads handed out by an atomic counter;
                          // 2: that grid for calls of at least kPersistentMinReads reads, else 0
   int groups_per_cu = 2; // persistent grid size = 256 CUs x groups_per_cu
-  int coop = 1;          // 1: VW/16 lanes per pair (q >= 5), 0: one lane per pair
+  int coop = 1;          // 1: VW/16 lanes per pair (q >= 5), 0: one lane per pair,
+                         // 2 (q = 5): four reads per wavefront, 16 lanes each
 };
 constexpr uint64_t kPersistentMinReads = 1ull << 20;
+// The launch shape an untuned index uses, by vector size: at q = 5 four reads
+// per wavefront in workgroups of 2 wavefronts (measured best on the short
+// lists of the 100 Mbp workload); at q = 6 and 7 groups of lanes per pair, 4
+// wavefronts per workgroup; otherwise one lane per pair.
+inline CandConfig default_cand_config(uint32_t vec_words) {
+  CandConfig c;
+  if (vec_words == 32) {
+    c.coop = 2;
+    c.waves = 2;
+  } else if (vec_words > 32 && vec_words <= 512) {
+    c.coop = 1;
+    c.waves = 4;
+  } else {
+    c.coop = 0;
+  }
+  return c;
+}
 hipError_t launch_scan_candidates(const CandArgs& a, const CandConfig& cfg, hipStream_t s);
 // Zero `n` uint32 words with a kernel (graph-safe, unlike a memset node).
 hipError_t launch_zero_words(uint32_t* p, uint32_t n, hipStream_t s);

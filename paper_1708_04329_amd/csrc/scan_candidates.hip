@@ -155,11 +155,14 @@ __device__ __forceinline__ void cand_read(const CandArgs& a, uint64_t r, uint64_
   wave_sync();
 }
 
-// Cooperative layout: G = VW / WPL lanes per pair, lane j streams words
-// [WPL j, WPL j + WPL) of the bin's vector and keeps the same words of the
-// first four planes in registers for all of the read's pairs. WPL is 8 for
-// 32-word vectors (q = 5: fewer registers, more wavefronts in flight for the
-// short candidate lists of that mode) and 16 above.
+// Cooperative layout: G = VW / WPL lanes per pair; lane j takes the 16-byte
+// chunks j, G + j, 2G + j, ... (WPL words) of the bin's vector and keeps the
+// same words of the first four planes in registers for all of the read's
+// pairs. Each load instruction then covers G * 16 contiguous bytes of every
+// vector it touches, so the texture units see whole 64-byte sectors instead
+// of a quarter of one per lane. WPL is 8 for 32-word vectors (q = 5: fewer
+// registers, more wavefronts in flight for the short candidate lists of that
+// mode) and 16 above.
 template <int VW>
 __device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, uint64_t n_cand,
                                                uint32_t* planes, uint32_t lane) {
@@ -178,7 +181,7 @@ __device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, ui
     if ((uint32_t)k < K) {
 #pragma unroll
       for (int w4 = 0; w4 < WPL / 4; ++w4) {
-        const uint4 p = reinterpret_cast<const uint4*>(planes + k * VW + WPL * j)[w4];
+        const uint4 p = reinterpret_cast<const uint4*>(planes + k * VW)[w4 * G + j];
         pl[k][4 * w4 + 0] = p.x; pl[k][4 * w4 + 1] = p.y; pl[k][4 * w4 + 2] = p.z; pl[k][4 * w4 + 3] = p.w;
       }
     } else {
@@ -202,11 +205,11 @@ __device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, ui
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       ok[u] = c[u] < c1 && x[u] >= 0 && (uint64_t)x[u] < a.nb;
-      const uint4* v4 = reinterpret_cast<const uint4*>(a.bm + (uint64_t)(ok[u] ? x[u] : 0) * VW + WPL * j);
+      const uint4* v4 = reinterpret_cast<const uint4*>(a.bm + (uint64_t)(ok[u] ? x[u] : 0) * VW);
 #pragma unroll
       for (int w4 = 0; w4 < WPL / 4; ++w4) {
         uint4 t = make_uint4(0, 0, 0, 0);
-        if (ok[u]) t = v4[w4];
+        if (ok[u]) t = v4[w4 * G + j];
         v[u][4 * w4 + 0] = t.x; v[u][4 * w4 + 1] = t.y; v[u][4 * w4 + 2] = t.z; v[u][4 * w4 + 3] = t.w;
       }
     }
@@ -224,7 +227,7 @@ __device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, ui
       }
       for (uint32_t k = 4; k < K; ++k) {  // rare: a token repeated 16 times or more
         uint32_t acc = 0;
-        for (int w = 0; w < WPL; ++w) acc += __popc(v[u][w] & planes[k * VW + WPL * j + w]);
+        for (int w = 0; w < WPL; ++w) acc += __popc(v[u][w] & planes[k * VW + ((w / 4) * G + j) * 4 + w % 4]);
         part += acc << k;
       }
       part = group_sum<G>(part);  // the group's partial counts (groups are aligned runs of G lanes)
@@ -241,26 +244,188 @@ __device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, ui
   wave_sync();
 }
 
-template <int VW, int NW, bool PERSISTENT, bool COOP>
+// Four reads per wavefront (q = 5, 128-byte vectors): the lists of that
+// mode are short (about 49 pairs per read on the 100 Mbp workload) and a
+// read's steps are a chain of dependent loads (offsets, tokens, plane build,
+// bin ids, vectors), so one read per wavefront leaves the chip waiting. Here
+// each 16-lane quarter of a wavefront takes its own read: four reads' chains
+// overlap, the plane builds of all four share the wavefront's two fences,
+// and each quarter keeps U = 4 pair passes of 4 pairs in flight. Per read
+// the steps are those of cand_read_coop: the planes are counted in LDS (16
+// planes of 32 words per read), K comes from an LDS maximum, each lane holds
+// words [8j, 8j + 8) of planes 0..3 in registers and ANDs them with the same
+// words of each candidate bin's vector, and the 4 lanes of a pair sum their
+// counts with DPP moves.
+constexpr int kQuadReads = 4;  // reads per wavefront in the quad layout
+
+template <int VW>
+__device__ __forceinline__ void cand_quad(const CandArgs& a, uint64_t r_first, uint64_t n_reads, uint64_t n_cand,
+                                          uint32_t* planes_wave, uint32_t lane) {
+  static_assert(VW == 32, "the quad layout is the q = 5 one");
+  constexpr int WPL = 8, G = VW / WPL, QL = 64 / kQuadReads, PPQ = QL / G, U = G;
+  constexpr uint32_t kPlaneWords = kMaxPlanes * VW;
+  const uint32_t qd = lane / QL, ql = lane % QL;
+  const uint64_t r = r_first + qd;
+  uint32_t* planes = planes_wave + qd * kPlaneWords;
+  uint32_t* kword = planes_wave + kQuadReads * kPlaneWords + qd;  // largest level reached, per read
+  int64_t c0 = 0, c1 = 0;
+  uint32_t ntok = 0;
+  int32_t T = 0;
+  const uint32_t* tok = a.tokens;
+  if (r < n_reads) {
+    c0 = a.cand_off[r];
+    c1 = a.cand_off[r + 1];
+    if (c0 < 0 || c1 < c0 || (uint64_t)c1 > n_cand) {
+      if (ql == 0) atomicOr(a.status, ST_BAD_CAND_OFF);
+      c0 = c1 = 0;
+    }
+    const int64_t o0 = a.offsets[r];
+    if (c1 > c0) ntok = (uint32_t)(a.offsets[r + 1] - o0 - a.q + 1);  // a read without pairs counts nothing
+    tok = a.tokens + token_base(o0, r);
+    T = a.thr[r];
+  }
+  uint4* p4 = reinterpret_cast<uint4*>(planes);
+  for (uint32_t i = ql; i < kPlaneWords / 4; i += QL) p4[i] = make_uint4(0, 0, 0, 0);
+  if (ql == 0) *kword = 0;
+  wave_sync();
+  const uint32_t R4 = a.R4;
+  uint32_t top = 0;  // highest level reached + 1
+  // four tokens per lane and load: a token list starts 16-byte aligned and its
+  // padding (code R4) reaches past the next multiple of 4 above the count
+  for (uint32_t i4 = ql * 4; i4 < ntok; i4 += 4 * QL) {
+    const uint4 t4 = ldg4(tok + i4);
+    const uint32_t tt[4] = {t4.x, t4.y, t4.z, t4.w};
+    // the four level-0 flips are issued together; a token whose bit was
+    // already set (a repeat) then carries into the levels above, in order
+    uint32_t old[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      old[e] = tt[e] < R4 ? atomicXor(planes + (tt[e] >> 5), 1u << (tt[e] & 31u)) : 0u;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t t = tt[e];
+      if (t >= R4) continue;  // invalid window or padding
+      const uint32_t bit = 1u << (t & 31u);
+      uint32_t k = 0;
+      if (old[e] & bit) {
+        uint32_t* w = planes + (t >> 5);
+        k = 1;
+        // a count stays below 2^16 (at most 65535 tokens), so k stays below kMaxPlanes
+        while ((atomicXor(w + k * VW, bit) & bit) && k + 1 < (uint32_t)kMaxPlanes) ++k;
+      }
+      top = max(top, k + 1);
+    }
+  }
+  if (top) atomicMax(kword, top);
+  wave_sync();
+  const uint32_t K = *kword;
+  const uint32_t j = ql % G, g = ql / G;
+  constexpr int NR = 2;  // planes held in registers (counts below 4); higher ones are read from LDS
+  uint32_t pl[NR][WPL];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if ((uint32_t)k < K) {
+#pragma unroll
+      for (int w4 = 0; w4 < WPL / 4; ++w4) {
+        const uint4 p = reinterpret_cast<const uint4*>(planes + k * VW)[w4 * G + j];
+        pl[k][4 * w4 + 0] = p.x; pl[k][4 * w4 + 1] = p.y; pl[k][4 * w4 + 2] = p.z; pl[k][4 * w4 + 3] = p.w;
+      }
+    } else {
+#pragma unroll
+      for (int w = 0; w < WPL; ++w) pl[k][w] = 0;
+    }
+  }
+  // An iteration covers U = G passes of PPQ pairs: pair pb + u * PPQ + g of the
+  // read goes to group g in pass u. Lane (g, j) loads the bin id of pass j and
+  // stores the result of pass j, so each of those takes one instruction for
+  // the whole wavefront; the bin ids reach the group's lanes by quad
+  // broadcasts. Vectors are loaded unconditionally (bin 0 stands in for pairs
+  // past the list's end and for bad bins, whose results are not stored), and
+  // pair indices are 32-bit offsets within the read's list.
+  const uint32_t npairs = (uint32_t)(c1 - c0);
+  const int32_t* cbin = a.cand_bin + c0;
+  uint16_t* cnt_out = a.count_out ? a.count_out + c0 : nullptr;
+  uint8_t* pas_out = a.pass_out ? a.pass_out + c0 : nullptr;
+  const uint32_t nb = (uint32_t)a.nb;  // at most 2^31 bins
+  for (uint32_t pb = 0; pb < npairs; pb += U * PPQ) {
+    const uint32_t pm = pb + j * PPQ + g;  // this lane's pair of pass j
+    const bool livem = pm < npairs;
+    const uint32_t xm = livem ? (uint32_t)cbin[pm] : 0u;
+    const bool okm = xm < nb;             // a negative bin id is caught here too
+    const uint32_t xs = okm ? xm : 0u;
+    uint32_t x[U];
+    x[0] = (uint32_t)__builtin_amdgcn_mov_dpp((int)xs, 0x00, 0xF, 0xF, false);  // quad_perm 0,0,0,0
+    x[1] = (uint32_t)__builtin_amdgcn_mov_dpp((int)xs, 0x55, 0xF, 0xF, false);  // quad_perm 1,1,1,1
+    x[2] = (uint32_t)__builtin_amdgcn_mov_dpp((int)xs, 0xAA, 0xF, 0xF, false);  // quad_perm 2,2,2,2
+    x[3] = (uint32_t)__builtin_amdgcn_mov_dpp((int)xs, 0xFF, 0xF, 0xF, false);  // quad_perm 3,3,3,3
+    uint32_t v[U][WPL];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint4* v4 = reinterpret_cast<const uint4*>(a.bm) + (uint64_t)x[u] * (VW / 4);
+#pragma unroll
+      for (int w4 = 0; w4 < WPL / 4; ++w4) {
+        const uint4 t = v4[w4 * G + j];
+        v[u][4 * w4 + 0] = t.x; v[u][4 * w4 + 1] = t.y; v[u][4 * w4 + 2] = t.z; v[u][4 * w4 + 3] = t.w;
+      }
+    }
+    uint32_t mine = 0;  // the group's count for pass j
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t part = 0;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        if ((uint32_t)k < K) {
+          uint32_t acc = 0;
+#pragma unroll
+          for (int w = 0; w < WPL; ++w) acc += __popc(v[u][w] & pl[k][w]);
+          part += acc << k;
+        }
+      }
+      for (uint32_t k = NR; k < K; ++k) {  // a token repeated 4 times or more
+        uint32_t acc = 0;
+        for (int w = 0; w < WPL; ++w) acc += __popc(v[u][w] & planes[k * VW + ((w / 4) * G + j) * 4 + w % 4]);
+        part += acc << k;
+      }
+      part = group_sum<G>(part);
+      if ((uint32_t)u == j) mine = part;
+    }
+    if (livem) {
+      if (!okm) {
+        atomicOr(a.status, ST_BAD_BIN);
+      } else {
+        if (cnt_out) cnt_out[pm] = (uint16_t)mine;
+        if (pas_out) pas_out[pm] = (int32_t)mine >= T ? 1 : 0;
+      }
+    }
+  }
+  // the LDS of this wavefront is reused by its next reads
+  wave_sync();
+}
+
+// LAYOUT: 0 one lane per pair, 1 VW/WPL lanes per pair, 2 four reads per
+// wavefront (q = 5). A wavefront's "step" is one read, or four in layout 2.
+template <int VW, int NW, bool PERSISTENT, int LAYOUT>
 __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
-  // one region per wavefront: the multiplicity planes (kMaxPlanes x VW words)
-  constexpr uint32_t kPerWave = kMaxPlanes * VW;
+  // one region per wavefront: the multiplicity planes (kMaxPlanes x VW words per read)
+  constexpr uint32_t kReads = LAYOUT == 2 ? kQuadReads : 1;
+  constexpr uint32_t kPerWave = kReads * kMaxPlanes * VW + (LAYOUT == 2 ? kQuadReads : 0);
   __shared__ __attribute__((aligned(16))) uint32_t lds[NW * kPerWave];
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   uint32_t* planes = lds + wave * kPerWave;
   const uint64_t n_reads = a.dyn ? min(a.dyn->n_reads, a.n_reads) : a.n_reads;
   const uint64_t n_cand = a.dyn ? min(a.dyn->n_cand, a.n_cand) : a.n_cand;
   if (a.status[0] & ~(uint32_t)(ST_BAD_BIN | ST_BAD_CAND_OFF)) return;  // rejected reads
-  auto one = [&](uint64_t r) {
-    if constexpr (COOP) cand_read_coop<VW>(a, r, n_cand, planes, lane);
+  auto step = [&](uint64_t r) {
+    if constexpr (LAYOUT == 2) cand_quad<VW>(a, r, n_reads, n_cand, planes, lane);
+    else if constexpr (LAYOUT == 1) cand_read_coop<VW>(a, r, n_cand, planes, lane);
     else cand_read<VW>(a, r, n_cand, planes, lane);
   };
   if constexpr (!PERSISTENT) {
-    const uint64_t r = (uint64_t)blockIdx.x * NW + wave;
-    if (r < n_reads) one(r);
+    const uint64_t r = ((uint64_t)blockIdx.x * NW + wave) * kReads;
+    if (r < n_reads) step(r);
   } else {
     // every wavefront leaves once the counter has passed n_reads; reads are
-    // taken a.grab at a time so the counter sees few atomics
+    // taken a.grab at a time (a multiple of kReads) so the counter sees few atomics
     const uint32_t grab = a.grab;
     while (true) {
       uint32_t r0 = 0;
@@ -268,13 +433,14 @@ __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
       r0 = __shfl(r0, 0);
       if ((uint64_t)r0 >= n_reads) break;
       const uint64_t r1 = min((uint64_t)r0 + grab, n_reads);
-      for (uint64_t r = r0; r < r1; ++r) one(r);
+      for (uint64_t r = r0; r < r1; r += kReads) step(r);
     }
   }
 }
 
-template <int VW, int NW, bool COOP>
+template <int VW, int NW, int LAYOUT>
 hipError_t launch_nw_layout(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
+  constexpr uint64_t kReads = LAYOUT == 2 ? kQuadReads : 1;
   const bool persistent = cfg.persistent == 1 || (cfg.persistent == 2 && a.n_reads >= kPersistentMinReads);
   if (persistent) {
     if (!a.work) return hipErrorInvalidValue;
@@ -285,25 +451,30 @@ hipError_t launch_nw_layout(const CandArgs& a, const CandConfig& cfg, hipStream_
     CandArgs b = a;
     const uint64_t per_read = std::max<uint64_t>(1, a.n_cand / std::max<uint64_t>(1, a.n_reads));
     const uint64_t spread = a.n_reads / (4 * blocks * NW);
-    b.grab = (uint32_t)std::min<uint64_t>(64, std::max<uint64_t>(1, std::min(8192 / per_read, spread)));
+    uint64_t grab = std::min<uint64_t>(64, std::max<uint64_t>(1, std::min(8192 / per_read, spread)));
+    b.grab = (uint32_t)((grab + kReads - 1) / kReads * kReads);
     hipError_t e = launch_zero_words(a.work, 1, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_scan_cand<VW, NW, true, COOP>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, b);
+    hipLaunchKernelGGL((k_scan_cand<VW, NW, true, LAYOUT>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, b);
   } else {
-    const uint64_t blocks = (a.n_reads + NW - 1) / NW;
+    const uint64_t per_block = NW * kReads;
+    const uint64_t blocks = (a.n_reads + per_block - 1) / per_block;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_scan_cand<VW, NW, false, COOP>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, a);
+    hipLaunchKernelGGL((k_scan_cand<VW, NW, false, LAYOUT>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, a);
   }
   return hipGetLastError();
 }
 
 template <int VW, int NW>
 hipError_t launch_nw(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
+  if constexpr (VW == 32) {
+    if (cfg.coop == 2) return launch_nw_layout<VW, NW, 2>(a, cfg, s);
+  }
   // the cooperative layout needs a pair's vector within one wavefront's lanes
   if constexpr (VW >= 32 && VW <= 512) {
-    if (cfg.coop) return launch_nw_layout<VW, NW, true>(a, cfg, s);
+    if (cfg.coop) return launch_nw_layout<VW, NW, 1>(a, cfg, s);
   }
-  return launch_nw_layout<VW, NW, false>(a, cfg, s);
+  return launch_nw_layout<VW, NW, 0>(a, cfg, s);
 }
 
 // LDS per wavefront: 16 * VW words; the wave count per group is capped so a
