@@ -236,28 +236,45 @@ hipError_t launch_build_bm(const BuildArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Reference copy for verification: one base code per byte (grid-stride loop,
-// the reference is read once, coalesced).
-__global__ __launch_bounds__(256) void k_ref_codes(const uint8_t* ref, uint64_t G, uint8_t* codes) {
+// Reference copy for verification: one base code per byte (0..3 for A, C, G,
+// T in either case, 4 for any other byte).
+//
+// Four bytes at once: with the case folded (l = b | 0x20), bits 1-2 and 2-3 of
+// a, c, g, t (0x61, 0x63, 0x67, 0x74) XOR to their codes 0, 1, 2, 3; a byte is
+// a base exactly when it equals the letter its code names, which one byte
+// permute looks up, and bytes that differ take code 4.
+__device__ __forceinline__ uint32_t ref_codes4(uint32_t w) {
+  const uint32_t l = w | 0x20202020u;
+  const uint32_t c = ((l >> 1) ^ (l >> 2)) & 0x03030303u;
+  const uint32_t letter = __builtin_amdgcn_perm(0u, 0x74676361u, c);  // byte k = "acgt"[c_k]
+  const uint32_t d = letter ^ l;
+  // 1 in each byte of d that is not zero (the add stays within the byte)
+  const uint32_t bad = ((((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u) >> 7;
+  return (c & ~(bad * 3u)) | (bad << 2);
+}
+
+// 16 bytes per lane when both pointers are 16-byte aligned (the copy is one
+// read and one write of G bytes); the last G % 16 bytes, or all of them for an
+// unaligned reference, go one byte per lane with the same arithmetic.
+__global__ __launch_bounds__(256) void k_ref_codes(const uint8_t* ref, uint64_t G, uint8_t* codes, bool vec) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G; i += stride) {
-    const uint8_t c = ref[i];
-    uint8_t v = 4;
-    switch (c | 0x20) {  // ASCII letters: fold to lower case
-      case 'a': v = 0; break;
-      case 'c': v = 1; break;
-      case 'g': v = 2; break;
-      case 't': v = 3; break;
-      default: break;
-    }
-    codes[i] = v;
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t n16 = vec ? G / 16 : 0;
+  const uint4* src = reinterpret_cast<const uint4*>(ref);
+  uint4* dst = reinterpret_cast<uint4*>(codes);
+  for (uint64_t i = tid; i < n16; i += stride) {
+    const uint4 t = src[i];
+    dst[i] = make_uint4(ref_codes4(t.x), ref_codes4(t.y), ref_codes4(t.z), ref_codes4(t.w));
   }
+  for (uint64_t i = n16 * 16 + tid; i < G; i += stride) codes[i] = (uint8_t)ref_codes4(ref[i]);
 }
 
 hipError_t launch_ref_codes(const uint8_t* ref, uint64_t G, uint8_t* codes, hipStream_t s) {
   if (G == 0) return hipSuccess;
-  const uint64_t blocks = std::min<uint64_t>((G + 255) / 256, 256ull * 64);
-  hipLaunchKernelGGL(k_ref_codes, dim3((unsigned)blocks), dim3(256), 0, s, ref, G, codes);
+  const bool vec = ((reinterpret_cast<uintptr_t>(ref) | reinterpret_cast<uintptr_t>(codes)) & 15u) == 0;
+  const uint64_t items = vec ? G / 16 + 16 : G;
+  const uint64_t blocks = std::min<uint64_t>((items + 255) / 256, 256ull * 8);
+  hipLaunchKernelGGL(k_ref_codes, dim3((unsigned)blocks), dim3(256), 0, s, ref, G, codes, vec);
   return hipGetLastError();
 }
 

@@ -384,6 +384,34 @@ def test_save_load_roundtrip(tmp_path):
     assert e.value.code == grim.GRIM_EIO
 
 
+@pytest.mark.parametrize("shift", [0, 3])
+def test_every_byte_value_in_the_reference(oracle, shift):
+    """A reference holding every byte value: the index bits follow the oracle (only
+    A, C, G, T in either case start a valid window) and the verification copy
+    holds codes 0..3 for those and 4 for every other byte. The length is not a
+    multiple of 16, and shift 3 hands the build a device pointer that is not
+    16-byte aligned."""
+    import torch
+    rng = random.Random(4242 + shift)
+    G = 100_003
+    ref = rand_ref(rng, G)
+    pos = rng.sample(range(G), 6000)
+    ref[pos] = np.arange(6000) % 256                    # every byte value, 23 times or more
+    codes = {ord(c): i for i, c in enumerate("ACGT")}
+    codes.update({ord(c): i for i, c in enumerate("acgt")})
+    want_codes = np.array([codes.get(int(b), 4) for b in ref], np.uint8)
+    B, O, q = 211, 40, 4
+    buf = torch.zeros(G + shift, dtype=torch.uint8, device="cuda")
+    buf[shift:] = dev(ref)
+    idx = grim.grim_build_index(buf[shift:], B, O, q, grim.LAYOUT_TM | grim.LAYOUT_BM | grim.LAYOUT_REF)
+    inf = idx.info()
+    assert np.array_equal(idx.read(grim.LAYOUT_REF), want_codes)
+    want = oracle.bits(ref, B, O, q)
+    nb, R4 = want.shape
+    assert np.array_equal(tm_to_bits(idx.read(grim.LAYOUT_TM), R4, inf["tm_row_words"], nb), want)
+    assert np.array_equal(bm_to_bits(idx.read(grim.LAYOUT_BM), R4, inf["bm_vec_words"], nb), want)
+
+
 # ---------------------------------------------------------------------------
 # q = 8: the largest token length the boundary takes (4^8-bit, 8 KB vectors)
 # ---------------------------------------------------------------------------
