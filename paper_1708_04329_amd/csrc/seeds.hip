@@ -13,14 +13,15 @@
 // read's candidates are its bins ranked by votes (more first), then by bin
 // (smaller first), the first `cap` kept, listed by increasing bin. On the GPU:
 //   1. hits per read (a thread per read: table lookups of its seeds);
-//   2. reads are cut into batches of bounded total hits; per batch
-//   3. every hit's bin is written out (a wavefront per read, coalesced reads
-//      of each seed's positions), 4. each read's bins are sorted (rocPRIM
-//      segmented radix sort on the bin's bits), 5. runs of equal bins become
-//      (bin, votes) (a wavefront per read, ballots mark run starts),
-//   6. reads with more than `cap` runs find the vote threshold by bisection
-//      with wavefront-wide counts, and every read writes its kept bins in bin
-//      order into the CSR output.
+//   2. reads are cut into batches whose staging (min(hits, cap) slots per
+//      read) is bounded, and sorted by hit count into four table sizes;
+//   3. a workgroup per read counts its bins' votes in an LDS hash table,
+//      picks the kept bins (vote threshold from a histogram, ties by a radix
+//      select on the bin) and writes them sorted to its staging slots;
+//   4. the few reads a table cannot describe exactly take a slower path in
+//      device memory (sort, runs, exact selection);
+//   5. a scan of the kept counts gives the CSR offsets, and the lists move
+//      from staging to their place.
 
 #include <algorithm>
 #include <cstdlib>
@@ -28,9 +29,6 @@
 #include <memory>
 #include <mutex>
 #include <vector>
-
-#include <rocprim/device/device_scan.hpp>
-#include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include "grim_internal.h"
 
@@ -47,21 +45,29 @@ struct grim_seeds {
   uint64_t* hits = nullptr;       // [n_reads] hits per read
   uint64_t* hits_host = nullptr;  // pinned copy
   uint64_t hits_cap = 0, hits_host_cap = 0;
-  uint32_t* seg = nullptr;        // [batch reads + 1] segment offsets
-  uint32_t* cnt = nullptr;        // [batch reads + 1] runs kept per read
-  uint32_t* nruns = nullptr;      // [batch reads + 1] runs per read
-  uint64_t* outoff = nullptr;     // [batch reads + 1] first output slot (batch-relative)
-  uint64_t batch_cap = 0;
-  uint32_t* keys_a = nullptr;     // [batch keys] bins, then run start positions
-  uint32_t* keys_b = nullptr;     // [batch keys] sorted bins
-  uint32_t* runs = nullptr;       // [batch keys] run bins
-  uint64_t keys_cap = 0;
-  void* tmp = nullptr;            // rocPRIM temporary storage
-  size_t tmp_cap = 0;
+  uint64_t* words = nullptr;      // [8]: CSR total so far (two words, by batch parity), bad offsets, fallback count
+  uint32_t* tmp = nullptr;        // staging: kept bins per read
+  uint64_t tmp_cap = 0;
+  uint64_t* toff = nullptr;       // [batch reads] first staging slot
+  uint64_t toff_cap = 0;
+  uint64_t* outoff = nullptr;     // [batch reads] CSR offset
+  uint64_t outoff_cap = 0;
+  uint64_t* bsum = nullptr;       // scan block sums
+  uint64_t bsum_cap = 0;
+  uint32_t* cnt = nullptr;        // [batch reads] bins kept
+  uint64_t cnt_cap = 0;
+  uint32_t* list = nullptr;       // [batch reads] reads grouped by table size
+  uint64_t list_cap = 0;
+  uint32_t* redo = nullptr;       // [batch reads] reads for the fallback
+  uint64_t redo_cap = 0;
+  uint32_t* slab = nullptr;       // fallback work space
+  uint64_t slab_cap = 0;
+  uint64_t* toff_host = nullptr;  // pinned
+  uint32_t* list_host = nullptr;  // pinned
+  uint64_t host_cap = 0;
   uint8_t* staging = nullptr;     // host-resident reads copied in
   uint64_t staging_cap = 0;
   uint64_t* total_host = nullptr; // pinned [4]
-  uint32_t* bad = nullptr;        // device word: a read's offsets were rejected
 };
 
 namespace grim {
@@ -177,27 +183,6 @@ __device__ __forceinline__ int64_t seed_code(const uint8_t* s, uint32_t k) {
   return (int64_t)code;
 }
 
-struct CandArgs2 {
-  const uint64_t* start;
-  const uint32_t* pos;
-  uint32_t k, B, cap;
-  const uint8_t* bases;
-  const int64_t* offsets;
-  uint64_t n_reads;
-  uint64_t r0;            // first read of the batch
-  uint64_t nb;            // reads in the batch
-  const uint32_t* seg;    // [nb + 1] key offsets of the batch's reads
-  uint32_t* keys_a;
-  uint32_t* keys_b;
-  uint32_t* runs;
-  uint32_t* cnt;
-  uint32_t* nruns;
-  const uint64_t* outoff;
-  uint64_t out_base;      // output slot of the batch's first candidate
-  int64_t* cand_off;
-  int32_t* cand_bin;
-};
-
 // A read whose offsets are out of order or outside [0, n_bases] gets no hits
 // and sets *bad; the call then fails before any later pass reads its bases.
 __global__ __launch_bounds__(256) void k_seed_hits(const uint64_t* start, uint32_t k, const uint8_t* bases,
@@ -221,78 +206,543 @@ __global__ __launch_bounds__(256) void k_seed_hits(const uint64_t* start, uint32
   hits[r] = h;
 }
 
-__device__ __forceinline__ uint64_t wave_uniform(uint64_t v) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+// ---------------------------------------------------------------------------
+// Exclusive prefix sums (uint32 in, uint64 out) in three passes: block sums,
+// one workgroup scanning them (plus an optional base held in device memory),
+// then each block's own elements.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kScanT = 256, kScanV = 16, kScanBlock = kScanT * kScanV;
+
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d) {
+  const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, d);
+  const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), d);
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Every hit's bin, in seed order, into the read's segment of keys_a.
-__global__ __launch_bounds__(256) void k_seed_expand(CandArgs2 a) {
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint64_t i = wave_uniform((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (i >= a.nb) return;
-  const uint64_t r = a.r0 + i;
-  const uint8_t* rd = a.bases + a.offsets[r];
-  const int64_t L = a.offsets[r + 1] - a.offsets[r];
-  uint64_t w = a.seg[i];
-  const int64_t n_seeds = L >= (int64_t)a.k ? L / (int64_t)a.k : 0;
-  // up to 64 seeds at a time: lane j codes seed sb + j and looks up its hit
-  // range, all in parallel; then the wavefront writes each seed's hits
-  for (int64_t sb = 0; sb < n_seeds; sb += 64) {
-    uint64_t h0 = 0, h1 = 0;
-    if (sb + lane < n_seeds) {
-      const int64_t c = seed_code(rd + (sb + lane) * a.k, a.k);
-      if (c >= 0) {
-        h0 = a.start[c];
-        h1 = a.start[c + 1];
-      }
+// Exclusive scan over the workgroup (T threads); *total receives the sum.
+template <int T, typename V>
+__device__ __forceinline__ V block_excl_scan(V v, V* ws, V* total) {
+  const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+  V x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    V y;
+    if constexpr (sizeof(V) == 8) y = shfl_up64(x, d);
+    else y = (V)__shfl_up((int)x, d);
+    if ((int)lane >= d) x += y;
+  }
+  if (lane == 63) ws[w] = x;
+  __syncthreads();
+  if (t == 0) {
+    V run = 0;
+    for (int i = 0; i < T / 64; ++i) {
+      const V s = ws[i];
+      ws[i] = run;
+      run += s;
     }
-    const int64_t m = min<int64_t>(64, n_seeds - sb);
-    for (int64_t j = 0; j < m; ++j) {
-      const uint64_t H0 = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(h0 >> 32), (int)j) << 32) |
-                          (uint32_t)__shfl((int)(uint32_t)h0, (int)j);
-      const uint64_t H1 = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(h1 >> 32), (int)j) << 32) |
-                          (uint32_t)__shfl((int)(uint32_t)h1, (int)j);
-      const int64_t o = (sb + j) * (int64_t)a.k;
-      for (uint64_t h = H0 + lane; h < H1; h += 64) {
-        const int64_t loc = (int64_t)a.pos[h] - o;
-        a.keys_a[w + (h - H0)] = (uint32_t)((loc < 0 ? 0 : loc) / a.B);
+    ws[T / 64] = run;
+  }
+  __syncthreads();
+  const V r = ws[w] + x - v;
+  *total = ws[T / 64];
+  __syncthreads();  // ws is reused by the next call
+  return r;
+}
+
+__global__ __launch_bounds__(kScanT) void k_scan_sums(const uint32_t* in, uint64_t n, uint64_t* bsum) {
+  __shared__ uint64_t ws[kScanT / 64 + 1];
+  const uint64_t b0 = (uint64_t)blockIdx.x * kScanBlock;
+  uint64_t s = 0;
+  for (uint64_t i = b0 + threadIdx.x; i < n && i < b0 + kScanBlock; i += kScanT) s += in[i];
+  uint64_t total;
+  (void)block_excl_scan<kScanT, uint64_t>(s, ws, &total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// One workgroup: bsum[] becomes exclusive offsets (plus *base); *total_out = *base + sum.
+__global__ __launch_bounds__(1024) void k_scan_top(uint64_t* bsum, uint64_t nblk, const uint64_t* base,
+                                                   uint64_t* total_out) {
+  __shared__ uint64_t ws[1024 / 64 + 1];
+  uint64_t carry = base ? *base : 0;
+  for (uint64_t c0 = 0; c0 < nblk; c0 += 1024) {
+    const uint64_t i = c0 + threadIdx.x;
+    const uint64_t v = i < nblk ? bsum[i] : 0;
+    uint64_t total;
+    const uint64_t ex = block_excl_scan<1024, uint64_t>(v, ws, &total);
+    if (i < nblk) bsum[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+__global__ __launch_bounds__(kScanT) void k_scan_apply(const uint32_t* in, uint64_t n, const uint64_t* boff,
+                                                       uint64_t* out) {
+  __shared__ uint64_t ws[kScanT / 64 + 1];
+  const uint64_t b0 = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanV;
+  uint32_t v[kScanV];
+  uint64_t s = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kScanV; ++j) {
+    v[j] = b0 + j < n ? in[b0 + j] : 0u;
+    s += v[j];
+  }
+  uint64_t total;
+  uint64_t run = boff[blockIdx.x] + block_excl_scan<kScanT, uint64_t>(s, ws, &total);
+#pragma unroll
+  for (uint32_t j = 0; j < kScanV; ++j) {
+    if (b0 + j < n) out[b0 + j] = run;
+    run += v[j];
+  }
+}
+
+// out[i] = (*base or 0) + in[0] + ... + in[i - 1]; *total_out = (*base or 0) + sum of in.
+// bsum needs scan_blocks(n) words.
+uint64_t scan_blocks(uint64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
+
+hipError_t launch_scan(const uint32_t* in, uint64_t n, uint64_t* out, uint64_t* bsum, const uint64_t* base,
+                       uint64_t* total_out, hipStream_t s) {
+  const uint64_t nblk = scan_blocks(n);
+  if (nblk) {
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nblk), dim3(kScanT), 0, s, in, n, bsum);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nblk, base, total_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !nblk) return e;
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblk), dim3(kScanT), 0, s, in, n, bsum, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Candidate selection, one workgroup per read, in LDS.
+//
+// Each hit's bin goes into an open-addressing hash table of packed entries
+// (bin << vb | votes, linear probing, atomic compare-and-swap to claim a
+// slot, atomic add to vote). With the table complete, a vote histogram gives
+// the read's distinct bins D. If D <= cap every bin is kept; otherwise the
+// kept bins are those with more votes than a threshold vt plus, among the
+// bins with exactly vt votes, the `need` smallest: the largest such bin is
+// found by a radix select over the table (8 bits of the bin per pass). The
+// kept bins are compacted to the front of the table, sorted with a bitonic
+// network, and written to the read's staging slots.
+//
+// A read whose hits do not fit the largest table is taken in R ranges of
+// bins, ascending: one pass over the ranges gathers the vote histogram, a
+// second keeps each range's share (the tie budget running across ranges)
+// and appends it. A range that fills its table restarts the read with twice
+// the ranges.
+//
+// Reads the table cannot describe exactly go to the fallback below: a bin
+// with 2^vb - 1 votes (the packed vote field would overflow), or a vote
+// threshold of 256 or more.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kVoteHist = 256;  // votes counted exactly below this
+
+struct SelArgs {
+  const uint64_t* start;
+  const uint32_t* pos;
+  uint32_t k;
+  const uint8_t* bases;
+  const int64_t* offsets;
+  uint64_t r0;               // first read of the batch
+  const uint64_t* hits;      // [n_reads] hits per read
+  const uint64_t* tmp_off;   // [batch reads] first staging slot of each read
+  uint32_t* tmp;             // staging: each read's kept bins, ascending
+  uint32_t* cnt;             // [batch reads] bins kept
+  uint32_t* redo;            // [batch reads] reads handed to the fallback
+  uint32_t* n_redo;          // their number
+  const uint32_t* list;      // batch-relative reads of this launch
+  uint32_t n_list;
+  uint32_t cap;
+  uint32_t nbins;            // bins are below nbins
+  uint32_t bin_bits;         // bits of nbins - 1
+  uint32_t vb;               // vote bits of a table entry
+  uint32_t dm, ds1, ds2;     // loc / B as (t + ((loc - t) >> ds1)) >> ds2, t = umulhi(dm, loc)
+  uint32_t range_hits;       // hits per range for reads taken in ranges
+  uint32_t force_ranges;     // take every read of the launch in ranges (tests)
+};
+
+__device__ __forceinline__ uint32_t hit_bin(uint32_t p, uint64_t o, const SelArgs& a) {
+  const uint32_t loc = (uint64_t)p > o ? (uint32_t)(p - o) : 0u;
+  const uint32_t t = __umulhi(a.dm, loc);
+  return (t + ((loc - t) >> a.ds1)) >> a.ds2;
+}
+
+// Ascending bitonic sort of d[0, N), N a power of two, by a workgroup of T threads.
+template <int T>
+__device__ void bitonic_sort(uint32_t* d, uint32_t N) {
+  for (uint32_t kk = 2; kk <= N; kk <<= 1) {
+    for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+      for (uint32_t q = threadIdx.x; q < N / 2; q += T) {
+        const uint32_t lo = ((q & ~(j - 1u)) << 1) | (q & (j - 1u));
+        const uint32_t hi = lo | j;
+        const uint32_t x = d[lo], y = d[hi];
+        if ((x > y) == ((lo & kk) == 0)) {
+          d[lo] = y;
+          d[hi] = x;
+        }
       }
-      w += H1 - H0;
+      __syncthreads();
     }
   }
 }
 
-// Runs of equal bins in each sorted segment: run j of read i starts at key
-// position keys_a[s0 + j] (overwriting the consumed bins) with bin runs[s0 + j];
-// cnt[i] = runs kept (at most cap).
-__global__ __launch_bounds__(256) void k_seed_runs(CandArgs2 a) {
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint64_t i = wave_uniform((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (i >= a.nb) return;
-  const uint32_t s0 = a.seg[i], s1 = a.seg[i + 1];
-  uint32_t nr = 0;
-  for (uint32_t c0 = s0; c0 < s1; c0 += 64) {
-    const uint32_t idx = c0 + lane;
-    const bool valid = idx < s1;
-    const uint32_t key = valid ? a.keys_b[idx] : 0u;
-    const bool st = valid && (idx == s0 || a.keys_b[idx - 1] != key);
-    const uint64_t m = __ballot(st);
-    if (st) {
-      const uint32_t j = nr + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-      a.keys_a[s0 + j] = idx;
-      a.runs[s0 + j] = key;
-    }
-    nr += (uint32_t)__popcll(m);
+// Inclusive scan over the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, uint32_t lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)x, d);
+    if ((int)lane >= d) x += y;
   }
-  if (lane == 0) {
-    a.cnt[i] = min(nr, a.cap);
-    a.nruns[i] = nr;
+  return x;
+}
+
+enum : uint32_t { kTiesNone = 0, kTiesAll = 1, kTiesUpTo = 2 };
+enum : uint32_t { kModeAll = 0, kModeSelect = 1, kModeFallback = 2 };
+
+template <int T, int SMAX>
+__global__ __launch_bounds__(T) void k_seed_select(SelArgs a) {
+  static_assert(SMAX % T == 0 && T % 64 == 0 && T <= 1024, "shape");
+  __shared__ uint32_t tab[SMAX];
+  __shared__ uint32_t hist[kVoteHist + 1];  // [v]: bins with v votes; [256]: 256 or more
+  __shared__ uint32_t dig[256];
+  __shared__ uint32_t s_h0[T];
+  __shared__ uint32_t s_pre[T + 1];
+  __shared__ uint32_t ws[T / 64 + 1];
+  // sh[0] slots claimed, [1] table at its limit, [2] vote field full,
+  // [3] mode, [4] vt, [5] need, [6] ties at vt, [7] digit, [8] count below it
+  __shared__ uint32_t sh[9];
+  const uint32_t t = threadIdx.x, lane = t & 63u;
+  const uint32_t vmask = (1u << a.vb) - 1u;
+  for (uint32_t li = blockIdx.x; li < a.n_list; li += gridDim.x) {
+    const uint32_t i = a.list[li];
+    const uint64_t r = a.r0 + i;
+    const uint64_t H = a.hits[r];
+    if (t == 0) sh[2] = 0;  // read by no thread before the first clear()'s barrier
+    const int64_t o0 = a.offsets[r];
+    const uint8_t* rd = a.bases + o0;
+    const uint32_t n_seeds = (uint32_t)((a.offsets[r + 1] - o0) / a.k);
+    auto room = [](uint32_t s) { return min(s / 4u * 3u, s - (uint32_t)T - 1u); };
+    uint32_t S = 2 * T;
+    while (S < (uint32_t)SMAX && room(S) < H) S <<= 1;
+    const uint32_t logS = 31u - __clz(S);
+    const uint32_t limit = room(S);
+    uint32_t R = 1;
+    if (room(S) < H || a.force_ranges) {
+      R = (uint32_t)min<uint64_t>((H + a.range_hits - 1) / a.range_hits, 1u << 16);
+      if (room(S) < H && R < 2) R = 2;
+      if (R == 0) R = 1;
+    }
+
+    auto clear = [&]() {
+      __syncthreads();  // every thread is done with the table and the flags
+      for (uint32_t s = t; s < S; s += T) tab[s] = kEmpty;
+      if (t == 0) {
+        sh[0] = 0;
+        sh[1] = 0;
+      }
+      __syncthreads();
+    };
+    auto insert = [&](uint32_t bin) {
+      uint32_t sl = (bin * 0x9E3779B1u) >> (32u - logS);
+      while (true) {
+        uint32_t e = tab[sl];
+        if (e == kEmpty) {
+          if (sh[1]) return;  // the table is at its limit: the read restarts
+          e = atomicCAS(&tab[sl], kEmpty, (bin << a.vb) | 1u);
+          if (e == kEmpty) {
+            if (atomicAdd(&sh[0], 1u) + 1u >= limit) sh[1] = 1u;
+            return;
+          }
+        }
+        if ((e >> a.vb) == bin) {
+          const uint32_t old = atomicAdd(&tab[sl], 1u);
+          if ((old & vmask) + 1u >= vmask) sh[2] = 1u;
+          return;
+        }
+        sl = (sl + 1u) & (S - 1u);
+      }
+    };
+    // every hit whose bin lies in [lo, hi) into the table
+    auto walk = [&](uint32_t lo, uint32_t hi) {
+      for (uint32_t sc = 0; sc < n_seeds; sc += T) {
+        const uint32_t ns = min((uint32_t)T, n_seeds - sc);
+        uint32_t h0 = 0, c = 0;
+        if (t < ns) {
+          const int64_t code = seed_code(rd + (uint64_t)(sc + t) * a.k, a.k);
+          if (code >= 0) {
+            const uint64_t b = a.start[code];
+            h0 = (uint32_t)b;
+            c = (uint32_t)(a.start[code + 1] - b);
+          }
+        }
+        uint32_t total;
+        const uint32_t ex = block_excl_scan<T, uint32_t>(c, ws, &total);
+        s_h0[t] = h0;
+        s_pre[t] = ex;  // threads past the chunk's seeds hold the total
+        if (t == 0) s_pre[T] = total;
+        __syncthreads();
+        uint32_t s = 0;
+        for (uint32_t f = t; f < total; f += T) {
+          while (s_pre[s + 1] <= f) ++s;
+          const uint32_t bin = hit_bin(a.pos[s_h0[s] + (f - s_pre[s])], (uint64_t)(sc + s) * a.k, a);
+          if (bin >= lo && bin < hi) insert(bin);
+        }
+        __syncthreads();  // the seed arrays are rewritten by the next chunk
+      }
+      __syncthreads();
+    };
+    // hist[] += the votes of the table's entries
+    auto histo = [&]() {
+      uint32_t n1 = 0, n2 = 0;
+      for (uint32_t sl = t; sl < S; sl += T) {  // S is a multiple of T
+        const uint32_t e = tab[sl];
+        const uint32_t v = e == kEmpty ? 0u : (e & vmask);
+        n1 += (uint32_t)__popcll(__ballot(v == 1u));
+        n2 += (uint32_t)__popcll(__ballot(v == 2u));
+        if (v > 2u) atomicAdd(&hist[min(v, kVoteHist)], 1u);
+      }
+      if (lane == 0) {
+        atomicAdd(&hist[1], n1);
+        atomicAdd(&hist[2], n2);
+      }
+      __syncthreads();
+    };
+    auto zero_hist = [&]() {
+      for (uint32_t v = t; v <= kVoteHist; v += T) hist[v] = 0;
+      __syncthreads();
+    };
+    // mode, vt, need and ties from hist (wavefront 0; lane l holds votes 4l .. 4l + 3)
+    auto decide = [&]() {
+      if (t < 64) {
+        uint32_t h[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) h[j] = hist[4 * lane + j];
+        const uint32_t top = hist[kVoteHist];
+        const uint32_t mine = h[0] + h[1] + h[2] + h[3];
+        // bins with more votes than this lane's range, and the total
+        const uint32_t incl = wave_incl_scan(mine, lane);
+        const uint32_t all = (uint32_t)__shfl((int)incl, 63) + top;
+        const uint32_t above = all - incl;  // votes > 4 lane + 3 (hist[0] is 0)
+        uint32_t vt = 0, run_vt = 0;
+        uint32_t run = above;
+        for (int j = 3; j >= 0; --j) {  // ge(4 lane + j) = run + h[j]
+          const uint32_t v = 4 * lane + (uint32_t)j;
+          if (!vt && v >= 1 && run + h[j] >= a.cap) {
+            vt = v;
+            run_vt = run;  // bins with more than vt votes
+          }
+          run += h[j];
+        }
+        // the largest vt: the highest lane that found one
+        const uint64_t m = __ballot(vt != 0);
+        if (lane == 0) {
+          if (all <= a.cap) {
+            sh[3] = kModeAll;
+          } else if (top >= a.cap || m == 0) {
+            sh[3] = kModeFallback;
+          } else {
+            sh[3] = kModeSelect;
+          }
+        }
+        if (m != 0 && lane == 63u - (uint32_t)__clzll(m)) {
+          sh[4] = vt;
+          sh[5] = a.cap - run_vt;
+          sh[6] = hist[vt];
+        }
+      }
+      __syncthreads();
+    };
+    // the want-th smallest bin among the entries with vt votes (radix select, 8 bits a pass)
+    auto select_bin = [&](uint32_t vt, uint32_t want) -> uint32_t {
+      uint32_t prefix = 0;
+      for (int hi = (int)a.bin_bits; hi > 0;) {
+        const int w = hi < 8 ? hi : 8, s = hi - w;
+        for (uint32_t d = t; d < 256; d += T) dig[d] = 0;
+        __syncthreads();
+        for (uint32_t sl = t; sl < S; sl += T) {
+          const uint32_t e = tab[sl];
+          if (e == kEmpty || (e & vmask) != vt) continue;
+          const uint32_t bin = e >> a.vb;
+          if (hi < 32 && (bin >> hi) != (prefix >> hi)) continue;
+          atomicAdd(&dig[(bin >> s) & ((1u << w) - 1u)], 1u);
+        }
+        __syncthreads();
+        if (t < 64) {
+          uint32_t c[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) c[j] = dig[4 * lane + j];
+          const uint32_t sum = c[0] + c[1] + c[2] + c[3];
+          const uint32_t incl = wave_incl_scan(sum, lane);
+          uint32_t cum = incl - sum;
+          if (cum < want && want <= incl) {
+            uint32_t d = 4 * lane;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              if (cum + c[j] >= want) break;
+              cum += c[j];
+              ++d;
+            }
+            sh[7] = d;
+            sh[8] = cum;
+          }
+        }
+        __syncthreads();
+        prefix |= sh[7] << s;
+        want -= sh[8];
+        hi = s;
+      }
+      return prefix;
+    };
+    // the kept entries of the table (all, or more than vt votes plus the ties the rule admits),
+    // ascending, to tmp[out_at ..]; returns their number
+    auto emit = [&](bool all, uint32_t vt, uint32_t ties, uint32_t bt, uint64_t out_at) -> uint32_t {
+      // compaction to the table's front, CH slots per thread at a time: a
+      // chunk's kept entries land below the chunk's end, in slots already read
+      constexpr uint32_t CH = 4;
+      uint32_t K = 0;
+      for (uint32_t c0 = 0; c0 < S; c0 += CH * T) {
+        uint32_t ev[CH];
+        uint32_t kmask = 0, nk = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < CH; ++j) {
+          const uint32_t sl = c0 + j * T + t;
+          const uint32_t e = sl < S ? tab[sl] : kEmpty;
+          ev[j] = e;
+          bool keep = false;
+          if (e != kEmpty) {
+            const uint32_t v = e & vmask;
+            keep = all || v > vt ||
+                   (v == vt && (ties == kTiesAll || (ties == kTiesUpTo && (e >> a.vb) <= bt)));
+          }
+          kmask |= (uint32_t)keep << j;
+          nk += keep ? 1u : 0u;
+        }
+        uint32_t chunk;
+        uint32_t p = K + block_excl_scan<T, uint32_t>(nk, ws, &chunk);  // the chunk's reads are done
+#pragma unroll
+        for (uint32_t j = 0; j < CH; ++j)
+          if ((kmask >> j) & 1u) tab[p++] = ev[j] >> a.vb;
+        K += chunk;
+      }
+      const uint32_t N = K <= 1 ? K : 1u << (32 - __clz(K - 1u));
+      __syncthreads();
+      for (uint32_t q = K + t; q < N; q += T) tab[q] = kEmpty;
+      __syncthreads();
+      bitonic_sort<T>(tab, N);
+      for (uint32_t q = t; q < K; q += T) a.tmp[out_at + q] = tab[q];
+      return K;
+    };
+
+    const uint64_t out0 = a.tmp_off[i];
+    bool fallback = false;
+    uint32_t kept = 0;
+    if (R == 1) {
+      clear();
+      walk(0, 0xFFFFFFFFu);
+      if (sh[2]) {
+        fallback = true;
+      } else {
+        zero_hist();
+        histo();
+        decide();
+        const uint32_t mode = sh[3];
+        if (mode == kModeFallback) {
+          fallback = true;
+        } else if (mode == kModeAll) {
+          kept = emit(true, 0, kTiesNone, 0, out0);
+        } else {
+          const uint32_t vt = sh[4], need = sh[5], ties = sh[6];
+          if (need < ties) kept = emit(false, vt, kTiesUpTo, select_bin(vt, need), out0);
+          else kept = emit(false, vt, kTiesAll, 0, out0);
+        }
+      }
+    } else {
+      const uint64_t nbins = a.nbins;
+      while (true) {
+        const uint64_t W = (nbins + R - 1) / R;
+        auto lo_of = [&](uint32_t j) { return (uint32_t)min<uint64_t>((uint64_t)j * W, 0xFFFFFFFFull); };
+        auto hi_of = [&](uint32_t j) { return (uint32_t)min<uint64_t>((uint64_t)(j + 1) * W, 0xFFFFFFFFull); };
+        // pass 1: the vote histogram over every range
+        zero_hist();
+        bool restart = false;
+        for (uint32_t j = 0; j < R && !restart && !fallback; ++j) {
+          clear();
+          walk(lo_of(j), hi_of(j));
+          if (sh[1]) restart = true;
+          else if (sh[2]) fallback = true;
+          else histo();
+        }
+        if (fallback) break;
+        if (restart) {
+          if (R >= (1u << 16)) {
+            fallback = true;
+            break;
+          }
+          R *= 2;
+          continue;
+        }
+        decide();
+        const uint32_t mode = sh[3];
+        if (mode == kModeFallback) {
+          fallback = true;
+          break;
+        }
+        const uint32_t vt = sh[4];
+        uint32_t need_left = mode == kModeSelect ? sh[5] : 0;
+        const bool cut = mode == kModeSelect && sh[5] < sh[6];
+        // pass 2: each range's kept bins, appended in bin order
+        kept = 0;
+        for (uint32_t j = 0; j < R; ++j) {
+          clear();
+          walk(lo_of(j), hi_of(j));
+          if (mode == kModeAll) {
+            kept += emit(true, 0, kTiesNone, 0, out0 + kept);
+            continue;
+          }
+          if (!cut) {
+            kept += emit(false, vt, kTiesAll, 0, out0 + kept);
+            continue;
+          }
+          zero_hist();
+          histo();
+          const uint32_t ties_here = hist[vt];
+          __syncthreads();
+          if (need_left == 0) {
+            kept += emit(false, vt, kTiesNone, 0, out0 + kept);
+          } else if (ties_here <= need_left) {
+            kept += emit(false, vt, kTiesAll, 0, out0 + kept);
+            need_left -= ties_here;
+          } else {
+            kept += emit(false, vt, kTiesUpTo, select_bin(vt, need_left), out0 + kept);
+            need_left = 0;
+          }
+        }
+        break;
+      }
+    }
+    if (t == 0) {
+      if (fallback) {
+        a.cnt[i] = 0;
+        a.redo[atomicAdd(a.n_redo, 1u)] = i;
+      } else {
+        a.cnt[i] = kept;
+      }
+    }
+    __syncthreads();
   }
 }
 
-// Votes of run j of a read whose runs start at rs[0 .. nr) within [.., s1).
+// ---------------------------------------------------------------------------
+// Fallback, one wavefront per read: every hit's bin into the wavefront's slab
+// of device memory, a bitonic sort there, runs of equal bins become (bin,
+// votes), and the kept runs are chosen exactly (vote threshold by counting,
+// ties by bin).
+// ---------------------------------------------------------------------------
+
+// Votes of run j of a read whose runs start at rs[0 .. nr) within [0, s1).
 __device__ __forceinline__ uint32_t run_votes(const uint32_t* rs, uint32_t j, uint32_t nr, uint32_t s1) {
   return (j + 1 < nr ? rs[j + 1] : s1) - rs[j];
 }
@@ -308,73 +758,114 @@ __device__ __forceinline__ uint32_t count_at_least(const uint32_t* rs, uint32_t 
   return c;
 }
 
-__global__ __launch_bounds__(256) void k_seed_select(CandArgs2 a) {
+__global__ __launch_bounds__(64) void k_seed_fallback(SelArgs a, uint32_t* slab, uint64_t slab_words) {
+  const uint32_t lane = threadIdx.x;
+  uint32_t* keys = slab + (uint64_t)blockIdx.x * slab_words;
+  const uint32_t n_redo = *a.n_redo;
+  for (uint32_t jr = blockIdx.x; jr < n_redo; jr += gridDim.x) {
+    const uint32_t i = a.redo[jr];
+    const uint64_t r = a.r0 + i;
+    const uint32_t H = (uint32_t)a.hits[r];
+    const uint32_t N = H <= 1 ? H : 1u << (32 - __clz(H - 1u));
+    uint32_t* rs = keys + N;  // run starts
+    uint32_t* rb = rs + H;    // run bins
+    const int64_t o0 = a.offsets[r];
+    const uint8_t* rd = a.bases + o0;
+    const uint32_t n_seeds = (uint32_t)((a.offsets[r + 1] - o0) / a.k);
+    // 1. every hit's bin, seed by seed (64 seeds' ranges looked up at once)
+    uint32_t w = 0;
+    for (uint32_t sb = 0; sb < n_seeds; sb += 64) {
+      uint64_t h0 = 0, h1 = 0;
+      if (sb + lane < n_seeds) {
+        const int64_t c = seed_code(rd + (uint64_t)(sb + lane) * a.k, a.k);
+        if (c >= 0) {
+          h0 = a.start[c];
+          h1 = a.start[c + 1];
+        }
+      }
+      const uint32_t m = min(64u, n_seeds - sb);
+      for (uint32_t j = 0; j < m; ++j) {
+        const uint32_t H0 = (uint32_t)__shfl((int)(uint32_t)h0, (int)j);
+        const uint32_t H1 = (uint32_t)__shfl((int)(uint32_t)h1, (int)j);
+        const uint64_t o = (uint64_t)(sb + j) * a.k;
+        for (uint32_t h = H0 + lane; h < H1; h += 64) keys[w + (h - H0)] = hit_bin(a.pos[h], o, a);
+        w += H1 - H0;
+      }
+    }
+    for (uint32_t q = H + lane; q < N; q += 64) keys[q] = kEmpty;
+    __syncthreads();
+    // 2. sort
+    bitonic_sort<64>(keys, N);
+    // 3. runs of equal bins
+    uint32_t nr = 0;
+    for (uint32_t c0 = 0; c0 < H; c0 += 64) {
+      const uint32_t idx = c0 + lane;
+      const bool valid = idx < H;
+      const uint32_t key = valid ? keys[idx] : 0u;
+      const bool st = valid && (idx == 0 || keys[idx - 1] != key);
+      const uint64_t mk = __ballot(st);
+      if (st) {
+        const uint32_t j = nr + (uint32_t)__popcll(mk & ((1ull << lane) - 1ull));
+        rs[j] = idx;
+        rb[j] = key;
+      }
+      nr += (uint32_t)__popcll(mk);
+    }
+    __syncthreads();
+    // 4. the kept runs, in bin order
+    uint32_t* out = a.tmp + a.tmp_off[i];
+    if (nr <= a.cap) {
+      for (uint32_t j = lane; j < nr; j += 64) out[j] = rb[j];
+      if (lane == 0) a.cnt[i] = nr;
+      __syncthreads();
+      continue;
+    }
+    // the largest v with at least cap runs of >= v votes (bisection; votes <= H)
+    uint32_t lo = 1, hi = H;
+    while (lo < hi) {
+      const uint32_t mid = lo + (hi - lo + 1) / 2;
+      if (count_at_least(rs, nr, H, mid, lane) >= a.cap) lo = mid;
+      else hi = mid - 1;
+    }
+    const uint32_t vt = lo;
+    const uint32_t need = a.cap - count_at_least(rs, nr, H, vt + 1, lane);
+    uint32_t taken = 0, ties = 0;
+    for (uint32_t j0 = 0; j0 < nr; j0 += 64) {
+      const uint32_t j = j0 + lane;
+      const uint32_t v = j < nr ? run_votes(rs, j, nr, H) : 0u;
+      const bool tie = j < nr && v == vt;
+      const uint64_t tm = __ballot(tie);
+      const uint32_t tie_rank = ties + (uint32_t)__popcll(tm & ((1ull << lane) - 1ull));
+      const bool keep = j < nr && (v > vt || (tie && tie_rank < need));
+      const uint64_t km = __ballot(keep);
+      if (keep) out[taken + (uint32_t)__popcll(km & ((1ull << lane) - 1ull))] = rb[j];
+      taken += (uint32_t)__popcll(km);
+      ties += (uint32_t)__popcll(tm);
+    }
+    if (lane == 0) a.cnt[i] = a.cap;
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Each read's kept bins from the staging slots to their place in the CSR
+// output (one wavefront per read); outoff already holds the absolute offsets.
+__global__ __launch_bounds__(256) void k_seed_place(const uint64_t* tmp_off, const uint32_t* tmp, const uint32_t* cnt,
+                                                    const uint64_t* outoff, uint64_t nb, uint64_t r0,
+                                                    int64_t* cand_off, int32_t* cand_bin) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t i = wave_uniform((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (i >= a.nb) return;
-  const uint64_t r = a.r0 + i;
-  const uint32_t s0 = a.seg[i], s1 = a.seg[i + 1];
-  const uint64_t out0 = a.out_base + a.outoff[i];
-  if (lane == 0) a.cand_off[r] = (int64_t)out0;
-  const uint32_t nr = a.nruns[i];  // runs of the read (cnt holds min(runs, cap))
-  const uint32_t* rs = a.keys_a + s0;
-  const uint32_t* rb = a.runs + s0;
-  if (nr <= a.cap) {
-    for (uint32_t j = lane; j < nr; j += 64) a.cand_bin[out0 + j] = (int32_t)rb[j];
-    return;
-  }
-  // the largest v with at least cap runs of >= v votes: one pass counts the
-  // runs at or above every v up to 32 (votes are few: one per seed); larger
-  // thresholds fall back to a bisection
-  constexpr uint32_t kHist = 32;
-  uint32_t ge[kHist + 1];
-#pragma unroll
-  for (uint32_t t = 0; t <= kHist; ++t) ge[t] = 0;
-  uint32_t vmax = 0;
-  for (uint32_t j0 = 0; j0 < nr; j0 += 64) {
-    const uint32_t j = j0 + lane;
-    const uint32_t v = j < nr ? run_votes(rs, j, nr, s1) : 0u;
-    vmax = max(vmax, v);
-#pragma unroll
-    for (uint32_t t = 1; t <= kHist; ++t) ge[t] += (uint32_t)__popcll(__ballot(v >= t));
-  }
-  for (int off = 32; off >= 1; off >>= 1) vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, off));
-  uint32_t lo = 1, hi = vmax;
-  if (ge[kHist] < a.cap) {
-    // the threshold is at most 32: the largest t with ge[t] >= cap (ge[1] = nr > cap)
-    uint32_t vt1 = 1;
-#pragma unroll
-    for (uint32_t t = 2; t <= kHist; ++t)
-      if (ge[t] >= a.cap) vt1 = t;
-    lo = hi = vt1;
-  } else {
-    lo = kHist;
-  }
-  while (lo < hi) {
-    const uint32_t mid = lo + (hi - lo + 1) / 2;
-    if (count_at_least(rs, nr, s1, mid, lane) >= a.cap) lo = mid;
-    else hi = mid - 1;
-  }
-  const uint32_t vt = lo;
-  // runs taken at exactly vt (ge is read with static indexes only, so it stays in registers)
-  uint32_t above = 0;
-#pragma unroll
-  for (uint32_t t = 2; t <= kHist; ++t)
-    if (t == vt + 1) above = ge[t];
-  const uint32_t need = a.cap - (vt < kHist ? above : count_at_least(rs, nr, s1, vt + 1, lane));
-  uint32_t taken = 0, ties = 0;
-  for (uint32_t j0 = 0; j0 < nr; j0 += 64) {
-    const uint32_t j = j0 + lane;
-    const uint32_t v = j < nr ? run_votes(rs, j, nr, s1) : 0;
-    const bool tie = j < nr && v == vt;
-    const uint64_t tm = __ballot(tie);
-    const uint32_t tie_rank = ties + (uint32_t)__popcll(tm & ((1ull << lane) - 1ull));
-    const bool keep = j < nr && (v > vt || (tie && tie_rank < need));
-    const uint64_t km = __ballot(keep);
-    if (keep) a.cand_bin[out0 + taken + (uint32_t)__popcll(km & ((1ull << lane) - 1ull))] = (int32_t)rb[j];
-    taken += (uint32_t)__popcll(km);
-    ties += (uint32_t)__popcll(tm);
-  }
+  if (i >= nb) return;
+  const uint64_t o = outoff[i];
+  if (lane == 0) cand_off[r0 + i] = (int64_t)o;
+  const uint32_t K = cnt[i];
+  const uint32_t* src = tmp + tmp_off[i];
+  for (uint32_t j = lane; j < K; j += 64) cand_bin[o + j] = (int32_t)src[j];
 }
 
 __global__ __launch_bounds__(256) void k_revcomp(const uint8_t* in, uint64_t n_bases, const int64_t* offsets, uint64_t n,
@@ -423,23 +914,48 @@ int grow_dev(T** p, uint64_t* cap, uint64_t need) {
 void free_seeds(grim_seeds* sd) {
   if (!sd) return;
   SeedGuard g(sd->device);
-  for (void* p : {(void*)sd->start, (void*)sd->pos, (void*)sd->hits, (void*)sd->seg, (void*)sd->cnt,
-                  (void*)sd->nruns, (void*)sd->outoff, (void*)sd->keys_a, (void*)sd->keys_b, (void*)sd->runs, sd->tmp,
-                  (void*)sd->staging, (void*)sd->bad})
+  for (void* p : {(void*)sd->start, (void*)sd->pos, (void*)sd->hits, (void*)sd->words, (void*)sd->tmp,
+                  (void*)sd->toff, (void*)sd->outoff, (void*)sd->bsum, (void*)sd->cnt, (void*)sd->list,
+                  (void*)sd->redo, (void*)sd->slab, (void*)sd->staging})
     if (p) (void)hipFree(p);
-  if (sd->hits_host) (void)hipHostFree(sd->hits_host);
-  if (sd->total_host) (void)hipHostFree(sd->total_host);
+  for (void* p : {(void*)sd->hits_host, (void*)sd->total_host, (void*)sd->toff_host, (void*)sd->list_host})
+    if (p) (void)hipHostFree(p);
   delete sd;
 }
 
-// Keys per batch of the candidate passes: 16 bytes of scratch per key
+// Staging slots per batch of the candidate passes, 4 bytes each
 // (GRIM_SEED_BATCH_KEYS overrides, e.g. to exercise many batches in tests).
 uint64_t batch_keys() {
   if (const char* e = std::getenv("GRIM_SEED_BATCH_KEYS")) {
     const long long v = std::atoll(e);
     if (v > 0) return (uint64_t)v;
   }
-  return 1ull << 29;
+  return 1ull << 28;
+}
+
+// Test switches: route reads to the larger tables, to bin ranges, or to the fallback.
+int env_int(const char* name, int dflt) {
+  const char* e = std::getenv(name);
+  return e && *e ? std::atoi(e) : dflt;
+}
+bool env_flag(const char* name) { return env_int(name, 0) != 0; }
+
+// Table size class of a read with h hits (h <= the class's 3/4-full table).
+uint32_t seed_class(uint64_t h) { return h <= 768 ? 0u : h <= 6144 ? 1u : h <= 12288 ? 2u : 3u; }
+
+// n / d for every 32-bit n as (t + ((n - t) >> s1)) >> s2 with t = umulhi(m, n)
+// (the round-up multiplier method of Granlund and Montgomery, 1994).
+void make_div(uint32_t d, uint32_t* m, uint32_t* s1, uint32_t* s2) {
+  if (d == 1) {
+    *m = 0;
+    *s1 = 0;
+    *s2 = 0;
+    return;
+  }
+  const uint32_t l = 32u - (uint32_t)__builtin_clz(d - 1);  // ceil(log2 d)
+  *m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+  *s1 = 1;
+  *s2 = l - 1;
 }
 
 }  // namespace
@@ -496,13 +1012,10 @@ int grim_seeds_build(const uint8_t* ref, uint64_t ref_len, uint32_t ref_on_devic
   hipLaunchKernelGGL(vec ? k_kmer_count<true> : k_kmer_count<false>, dim3((unsigned)blocks), dim3(256), 0, s, dref,
                      ref_len, k, counts);
   if ((e = hipGetLastError()) != hipSuccess) return fail(e, "k-mer count");
-  size_t tmp_bytes = 0;
-  if ((e = rocprim::exclusive_scan(nullptr, tmp_bytes, counts, sd->start, (uint64_t)0, (size_t)(sd->nk + 1),
-                                   rocprim::plus<uint64_t>(), s)) != hipSuccess)
-    return fail(e, "scan size");
-  if ((e = hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 1))) != hipSuccess) return fail(e, "scan storage");
-  if ((e = rocprim::exclusive_scan(tmp, tmp_bytes, counts, sd->start, (uint64_t)0, (size_t)(sd->nk + 1),
-                                   rocprim::plus<uint64_t>(), s)) != hipSuccess)
+  if ((e = hipMalloc(&tmp, (scan_blocks(sd->nk + 1) + 1) * sizeof(uint64_t))) != hipSuccess)
+    return fail(e, "scan storage");
+  if ((e = launch_scan(counts, sd->nk + 1, sd->start, static_cast<uint64_t*>(tmp), nullptr, nullptr, s)) !=
+      hipSuccess)
     return fail(e, "k-mer scan");
   uint64_t n_pos = 0;
   if ((e = hipMemcpyAsync(&n_pos, sd->start + sd->nk, sizeof n_pos, hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -577,132 +1090,159 @@ int grim_seed_candidates(const grim_seeds* csd, const grim_reads* rd, uint32_t b
     GRIM_HIP_TRY(hipHostMalloc(&sd->hits_host, sd->hits_cap * sizeof(uint64_t), hipHostMallocDefault));
     sd->hits_host_cap = sd->hits_cap;
   }
-  if (!sd->bad) GRIM_HIP_TRY(hipMalloc(&sd->bad, sizeof(uint32_t)));
-  GRIM_HIP_TRY(launch_zero_words(sd->bad, 1, s));
+  if (!sd->words) GRIM_HIP_TRY(hipMalloc(&sd->words, 8 * sizeof(uint64_t)));
+  uint32_t* bad = reinterpret_cast<uint32_t*>(sd->words + 2);
+  uint32_t* n_redo = reinterpret_cast<uint32_t*>(sd->words + 3);
+  GRIM_HIP_TRY(launch_zero_words(reinterpret_cast<uint32_t*>(sd->words), 16, s));  // base, bad, n_redo
   hipLaunchKernelGGL(k_seed_hits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, sd->start, sd->k, bases,
-                     rd->n_bases, offsets, n, sd->hits, sd->bad);
+                     rd->n_bases, offsets, n, sd->hits, bad);
   GRIM_HIP_TRY(hipGetLastError());
   GRIM_HIP_TRY(hipMemcpyAsync(sd->hits_host, sd->hits, n * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   uint32_t* bad_host = reinterpret_cast<uint32_t*>(sd->total_host + 3);
-  GRIM_HIP_TRY(hipMemcpyAsync(bad_host, sd->bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  GRIM_HIP_TRY(hipMemcpyAsync(bad_host, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   GRIM_HIP_TRY(hipStreamSynchronize(s));
   if (*bad_host) return set_error(GRIM_EINVAL, "read offsets out of order or outside [0, n_bases]");
   const uint64_t* H = sd->hits_host;
-  // largest bin index: max(p - o, 0) / B < G / B
+  // bins lie in [0, nbins): max(p - o, 0) / B <= (G - 1) / B
   const uint64_t max_bin = sd->G / bin_size;
   if (max_bin > 0x7FFFFFFFull) return set_error(GRIM_EINVAL, "more than 2^31 bins");
-  uint32_t end_bit = 1;
-  while (end_bit < 32 && (max_bin >> end_bit)) ++end_bit;
-  // 2. batches of bounded total hits
-  uint64_t out_base = 0;
+  const uint32_t nbins = (uint32_t)(max_bin + 1);
+  const uint32_t key_bits = 32u - (uint32_t)__builtin_clz(nbins);  // the all-ones key is no bin
+  uint32_t vb = 32u - key_bits;
+  if (const char* e = std::getenv("GRIM_SEED_VOTE_BITS")) vb = std::min<uint32_t>(vb, (uint32_t)std::max(1, std::atoi(e)));
+  const bool all_fallback = vb < 2 || env_flag("GRIM_SEED_FALLBACK_ALL");
+  const uint32_t class_min = (uint32_t)std::min(3, std::max(0, env_int("GRIM_SEED_CLASS_MIN", 0)));
+  SelArgs a{};
+  a.start = sd->start;
+  a.pos = sd->pos;
+  a.k = sd->k;
+  a.bases = bases;
+  a.offsets = offsets;
+  a.hits = sd->hits;
+  a.cap = cap;
+  a.nbins = nbins;
+  a.bin_bits = nbins <= 1 ? 1u : 32u - (uint32_t)__builtin_clz(nbins - 1);
+  a.vb = vb;
+  make_div(bin_size, &a.dm, &a.ds1, &a.ds2);
+  a.range_hits = (uint32_t)std::max(1, env_int("GRIM_SEED_RANGE_HITS", 16384));
+  a.force_ranges = env_flag("GRIM_SEED_FORCE_RANGES") ? 1u : 0u;
+  a.n_redo = n_redo;
+  // 2. batches of bounded staging: each read takes min(hits, cap) slots
   const uint64_t limit = batch_keys();
-  std::vector<uint32_t> seg_host;
-  for (uint64_t r0 = 0; r0 < n;) {
-    uint64_t r1 = r0, keys = 0;
-    while (r1 < n && (r1 == r0 || keys + H[r1] <= limit)) keys += H[r1++];
-    if (keys > 0xFFFFFFFFull - 64) return set_error(GRIM_ENOMEM, "seed hits of read %llu exceed 2^32", (unsigned long long)r0);
+  uint64_t nbatch = 0;
+  for (uint64_t r0 = 0; r0 < n; ++nbatch) {
+    uint64_t r1 = r0, slots = 0, max_h = 0;
+    while (r1 < n && (r1 == r0 || (slots + std::min<uint64_t>(H[r1], cap) <= limit && r1 - r0 < (1ull << 26)))) {
+      if (H[r1] > 0xFFFFFFFFull - 64)
+        return set_error(GRIM_ENOMEM, "seed hits of read %llu exceed 2^32", (unsigned long long)r1);
+      slots += std::min<uint64_t>(H[r1], cap);
+      max_h = std::max(max_h, H[r1]);
+      ++r1;
+    }
     const uint64_t nb = r1 - r0;
-    seg_host.assign(nb + 1, 0);
-    for (uint64_t i = 0; i < nb; ++i) seg_host[i + 1] = seg_host[i] + (uint32_t)H[r0 + i];
-    if (sd->batch_cap < nb + 1 || !sd->seg) {
-      for (void* p : {(void*)sd->seg, (void*)sd->cnt, (void*)sd->nruns, (void*)sd->outoff})
-        if (p) (void)hipFree(p);
-      sd->seg = nullptr;
-      sd->cnt = nullptr;
-      sd->nruns = nullptr;
-      sd->outoff = nullptr;
-      uint64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-      if ((rc = grow_dev(&sd->seg, &c0, nb + 1))) return rc;
-      if ((rc = grow_dev(&sd->cnt, &c1, c0))) return rc;
-      if ((rc = grow_dev(&sd->nruns, &c3, c0))) return rc;
-      if ((rc = grow_dev(&sd->outoff, &c2, c0))) return rc;
-      sd->batch_cap = c0;
+    // host side: staging offsets and the reads of each launch, grouped by table size
+    if (sd->host_cap < nb) {
+      if (sd->toff_host) (void)hipHostFree(sd->toff_host);
+      if (sd->list_host) (void)hipHostFree(sd->list_host);
+      sd->toff_host = nullptr;
+      sd->list_host = nullptr;
+      sd->host_cap = 0;
+      const uint64_t c = nb + nb / 8 + 64;
+      GRIM_HIP_TRY(hipHostMalloc(&sd->toff_host, c * sizeof(uint64_t), hipHostMallocDefault));
+      GRIM_HIP_TRY(hipHostMalloc(&sd->list_host, c * sizeof(uint32_t), hipHostMallocDefault));
+      sd->host_cap = c;
     }
-    uint64_t kc = sd->keys_cap;
-    if (sd->keys_cap < keys + 1 || !sd->keys_a) {
-      if (sd->keys_a) (void)hipFree(sd->keys_a);
-      if (sd->keys_b) (void)hipFree(sd->keys_b);
-      if (sd->runs) (void)hipFree(sd->runs);
-      sd->keys_a = sd->keys_b = sd->runs = nullptr;
-      kc = 0;
-      uint64_t c1 = 0, c2 = 0;
-      if ((rc = grow_dev(&sd->keys_a, &kc, keys + 1))) return rc;
-      if ((rc = grow_dev(&sd->keys_b, &c1, keys + 1))) return rc;
-      if ((rc = grow_dev(&sd->runs, &c2, keys + 1))) return rc;
-      sd->keys_cap = kc;
+    uint64_t per_class[4] = {0, 0, 0, 0}, n_fb = 0;
+    uint64_t run = 0;
+    for (uint64_t i = 0; i < nb; ++i) {
+      const uint64_t h = H[r0 + i];
+      sd->toff_host[i] = run;
+      run += std::min<uint64_t>(h, cap);
+      if (h == 0) continue;
+      if (all_fallback) {
+        ++n_fb;
+        continue;
+      }
+      ++per_class[std::max(class_min, seed_class(h))];
     }
-    GRIM_HIP_TRY(hipMemcpyAsync(sd->seg, seg_host.data(), (nb + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    CandArgs2 a{};
-    a.start = sd->start;
-    a.pos = sd->pos;
-    a.k = sd->k;
-    a.B = bin_size;
-    a.cap = cap;
-    a.bases = bases;
-    a.offsets = offsets;
-    a.n_reads = n;
+    uint64_t first[5] = {0, 0, 0, 0, 0};
+    for (int c = 0; c < 4; ++c) first[c + 1] = first[c] + per_class[c];
+    {
+      uint64_t at[4] = {first[0], first[1], first[2], first[3]};
+      uint64_t fb = 0;
+      for (uint64_t i = 0; i < nb; ++i) {
+        const uint64_t h = H[r0 + i];
+        if (h == 0) continue;
+        if (all_fallback) sd->list_host[fb++] = (uint32_t)i;
+        else sd->list_host[at[std::max(class_min, seed_class(h))]++] = (uint32_t)i;
+      }
+    }
+    const uint64_t listed = all_fallback ? n_fb : first[4];
+    if ((rc = grow_dev(&sd->tmp, &sd->tmp_cap, std::max<uint64_t>(slots, 1)))) return rc;
+    if ((rc = grow_dev(&sd->toff, &sd->toff_cap, nb))) return rc;
+    if ((rc = grow_dev(&sd->outoff, &sd->outoff_cap, nb))) return rc;
+    if ((rc = grow_dev(&sd->bsum, &sd->bsum_cap, scan_blocks(nb) + 1))) return rc;
+    if ((rc = grow_dev(&sd->cnt, &sd->cnt_cap, nb))) return rc;
+    if ((rc = grow_dev(&sd->list, &sd->list_cap, std::max<uint64_t>(listed, 1)))) return rc;
+    if ((rc = grow_dev(&sd->redo, &sd->redo_cap, nb))) return rc;
+    GRIM_HIP_TRY(hipMemcpyAsync(sd->toff, sd->toff_host, nb * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    GRIM_HIP_TRY(launch_zero_words(sd->cnt, (uint32_t)nb, s));
+    if (all_fallback) {
+      GRIM_HIP_TRY(hipMemcpyAsync(sd->redo, sd->list_host, std::max<uint64_t>(n_fb, 1) * sizeof(uint32_t),
+                                  hipMemcpyHostToDevice, s));
+      sd->total_host[1] = n_fb;
+      GRIM_HIP_TRY(hipMemcpyAsync(n_redo, sd->total_host + 1, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    } else {
+      if (listed)
+        GRIM_HIP_TRY(hipMemcpyAsync(sd->list, sd->list_host, listed * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+      GRIM_HIP_TRY(launch_zero_words(n_redo, 1, s));
+    }
     a.r0 = r0;
-    a.nb = nb;
-    a.seg = sd->seg;
-    a.keys_a = sd->keys_a;
-    a.keys_b = sd->keys_b;
-    a.runs = sd->runs;
+    a.tmp_off = sd->toff;
+    a.tmp = sd->tmp;
     a.cnt = sd->cnt;
-    a.nruns = sd->nruns;
-    a.outoff = sd->outoff;
-    a.out_base = out_base;
-    a.cand_off = cand_off;
-    a.cand_bin = cand_bin;
-    const unsigned wblocks = (unsigned)((nb + 3) / 4);
-    // 3. bins of every hit
-    hipLaunchKernelGGL(k_seed_expand, dim3(wblocks), dim3(256), 0, s, a);
-    GRIM_HIP_TRY(hipGetLastError());
-    // 4. sort each read's bins
-    size_t need = 0;
-    GRIM_HIP_TRY(rocprim::segmented_radix_sort_keys(nullptr, need, sd->keys_a, sd->keys_b, (unsigned)keys,
-                                                    (unsigned)nb, sd->seg, sd->seg + 1, 0u, end_bit, s));
-    if (need > sd->tmp_cap || !sd->tmp) {
-      if (sd->tmp) (void)hipFree(sd->tmp);
-      sd->tmp = nullptr;
-      sd->tmp_cap = 0;
-      GRIM_HIP_TRY(hipMalloc(&sd->tmp, std::max<size_t>(need, 1)));
-      sd->tmp_cap = std::max<size_t>(need, 1);
+    a.redo = sd->redo;
+    // 3. each read's kept bins, in LDS, one workgroup per read
+    if (!all_fallback) {
+      for (int c = 0; c < 4; ++c) {
+        if (!per_class[c]) continue;
+        SelArgs b = a;
+        b.list = sd->list + first[c];
+        b.n_list = (uint32_t)per_class[c];
+        const dim3 grid((unsigned)std::min<uint64_t>(per_class[c], 1u << 30));
+        switch (c) {
+          case 0: hipLaunchKernelGGL((k_seed_select<64, 1024>), grid, dim3(64), 0, s, b); break;
+          case 1: hipLaunchKernelGGL((k_seed_select<256, 8192>), grid, dim3(256), 0, s, b); break;
+          case 2: hipLaunchKernelGGL((k_seed_select<512, 16384>), grid, dim3(512), 0, s, b); break;
+          default: hipLaunchKernelGGL((k_seed_select<1024, 32768>), grid, dim3(1024), 0, s, b); break;
+        }
+        GRIM_HIP_TRY(hipGetLastError());
+      }
     }
-    size_t have = sd->tmp_cap;
-    GRIM_HIP_TRY(rocprim::segmented_radix_sort_keys(sd->tmp, have, sd->keys_a, sd->keys_b, (unsigned)keys,
-                                                    (unsigned)nb, sd->seg, sd->seg + 1, 0u, end_bit, s));
-    // 5. runs and kept counts
-    hipLaunchKernelGGL(k_seed_runs, dim3(wblocks), dim3(256), 0, s, a);
-    GRIM_HIP_TRY(hipGetLastError());
-    need = 0;
-    GRIM_HIP_TRY(rocprim::exclusive_scan(nullptr, need, sd->cnt, sd->outoff, (uint64_t)0, (size_t)nb,
-                                         rocprim::plus<uint64_t>(), s));
-    if (need > sd->tmp_cap) {
-      (void)hipFree(sd->tmp);
-      sd->tmp = nullptr;
-      sd->tmp_cap = 0;
-      GRIM_HIP_TRY(hipMalloc(&sd->tmp, need));
-      sd->tmp_cap = need;
+    // 4. reads the tables could not take (a wavefront each, in device memory)
+    {
+      const uint64_t np2 = max_h <= 1 ? 1 : 1ull << (64 - __builtin_clzll(max_h - 1));
+      const uint64_t slab_words = np2 + 2 * max_h + 64;
+      const uint64_t waves = std::max<uint64_t>(1, std::min<uint64_t>(512, (128ull << 20) / (slab_words * 4)));
+      if ((rc = grow_dev(&sd->slab, &sd->slab_cap, slab_words * waves))) return rc;
+      hipLaunchKernelGGL(k_seed_fallback, dim3((unsigned)waves), dim3(64), 0, s, a, sd->slab, slab_words);
+      GRIM_HIP_TRY(hipGetLastError());
     }
-    have = sd->tmp_cap;
-    GRIM_HIP_TRY(rocprim::exclusive_scan(sd->tmp, have, sd->cnt, sd->outoff, (uint64_t)0, (size_t)nb,
-                                         rocprim::plus<uint64_t>(), s));
-    // 6. kept bins in bin order
-    hipLaunchKernelGGL(k_seed_select, dim3(wblocks), dim3(256), 0, s, a);
+    // 5. CSR offsets (continuing the previous batches' total) and the lists in place
+    uint64_t* base_in = sd->words + (nbatch & 1);
+    uint64_t* base_out = sd->words + ((nbatch + 1) & 1);
+    GRIM_HIP_TRY(launch_scan(sd->cnt, nb, sd->outoff, sd->bsum, base_in, base_out, s));
+    hipLaunchKernelGGL(k_seed_place, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, sd->toff, sd->tmp, sd->cnt,
+                       sd->outoff, nb, r0, cand_off, cand_bin);
     GRIM_HIP_TRY(hipGetLastError());
-    // batch total: last offset + last count
-    uint32_t last_cnt = 0;
-    GRIM_HIP_TRY(hipMemcpyAsync(sd->total_host, sd->outoff + nb - 1, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    GRIM_HIP_TRY(hipMemcpyAsync(sd->total_host + 1, sd->cnt + nb - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    GRIM_HIP_TRY(hipStreamSynchronize(s));
-    std::memcpy(&last_cnt, sd->total_host + 1, sizeof last_cnt);
-    out_base += sd->total_host[0] + last_cnt;
+    GRIM_HIP_TRY(hipStreamSynchronize(s));  // the host arrays are refilled by the next batch
     r0 = r1;
   }
-  sd->total_host[2] = out_base;
+  GRIM_HIP_TRY(hipMemcpyAsync(sd->total_host + 2, sd->words + (nbatch & 1), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  GRIM_HIP_TRY(hipStreamSynchronize(s));
   GRIM_HIP_TRY(hipMemcpyAsync(cand_off + n, sd->total_host + 2, sizeof(int64_t), hipMemcpyHostToDevice, s));
   GRIM_HIP_TRY(hipStreamSynchronize(s));
-  *n_cand_out = out_base;
+  *n_cand_out = sd->total_host[2];
   return GRIM_OK;
 }
 

@@ -150,6 +150,48 @@ def test_seed_candidates_recipes(oracle, key):
     log(key, "candidates", len(got[1]))
 
 
+@pytest.mark.parametrize("k,B,cap", [(6, 97, 5), (5, 211, 50), (4, 1000, 1024), (4, 61, 7), (5, 300, 100000)])
+def test_seed_candidates_dense_hits(oracle, k, B, cap):
+    """Short seeds on a 200 kbp genome give reads from a few dozen to tens of
+    thousands of hits: every table size, reads taken in bin ranges, caps that
+    cut ties, keep everything or fall below the distinct bins."""
+    rng = random.Random(400 + 10 * k + cap % 97)
+    ref = rand_genome(rng, 200_000)
+    rd = rand_reads(rng, ref, 300)
+    seeds = grim.grim_seeds_build(dev(ref), k)
+    got = gpu_candidates(seeds, rd, B, cap)
+    want = oracle.seed_candidates(ref, rd.bases, rd.offsets, k, B, cap)
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+    log("dense hits k", k, "B", B, "cap", cap, "candidates", len(got[1]))
+
+
+SEED_PATHS = {
+    "largest_table": {"GRIM_SEED_CLASS_MIN": "3"},
+    "bin_ranges": {"GRIM_SEED_CLASS_MIN": "3", "GRIM_SEED_FORCE_RANGES": "1", "GRIM_SEED_RANGE_HITS": "37"},
+    "vote_field_full": {"GRIM_SEED_VOTE_BITS": "2"},
+    "fallback_only": {"GRIM_SEED_FALLBACK_ALL": "1"},
+}
+
+
+@pytest.mark.parametrize("path", sorted(SEED_PATHS))
+@pytest.mark.parametrize("cap", [1, 6, 64, 5000])
+def test_seed_candidate_paths_match_oracle(oracle, monkeypatch, path, cap):
+    """Each route a read can take gives the oracle's lists: the largest LDS
+    table for every read; every read split into bin ranges (the tie budget
+    running across ranges); a vote field so narrow that reads overflow it and
+    go to the device-memory fallback; the fallback for every read."""
+    for key, val in SEED_PATHS[path].items():
+        monkeypatch.setenv(key, val)
+    rng = random.Random(77 + cap)
+    ref = rand_genome(rng, 120_000)
+    rd = rand_reads(rng, ref, 250)
+    for k, B in ((6, 150), (8, 1000)):
+        seeds = grim.grim_seeds_build(dev(ref), k)
+        got = gpu_candidates(seeds, rd, B, cap)
+        want = oracle.seed_candidates(ref, rd.bases, rd.offsets, k, B, cap)
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), (path, k, B, cap)
+
+
 def test_reverse_complement():
     import torch
     seqs = [b"ACGTN", b"aacgT", b"", b"GGGCCCATN-x"]
