@@ -267,6 +267,7 @@ CandConfig cand_config_from_env(CandConfig c) {
     const int v = std::atoi(t);
     c.coop = v == 2 ? 2 : (v ? 1 : 0);
   }
+  if (const char* t = std::getenv("GRIM_CAND_PLANES")) c.planes = std::atoi(t) == 16 ? 16 : 8;
   if (c.waves < 0 || c.waves > 8) c.waves = 0;
   if (c.groups_per_cu < 1 || c.groups_per_cu > 64) c.groups_per_cu = 2;
   return c;

@@ -233,6 +233,8 @@ struct CandConfig {
   int groups_per_cu = 2; // persistent grid size = 256 CUs x groups_per_cu
   int coop = 1;          // 1: VW/16 lanes per pair (q >= 5), 0: one lane per pair,
                          // 2 (q = 5): four reads per wavefront, 16 lanes each
+  int planes = 8;        // coop 2: LDS planes per read, 8 (reads above 255 tokens in a
+                         // second pass) or 16
 };
 constexpr uint64_t kPersistentMinReads = 1ull << 20;
 // The launch shape an untuned index uses, by vector size: at q = 5 four reads

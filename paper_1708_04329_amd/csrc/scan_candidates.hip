@@ -256,14 +256,22 @@ __device__ __forceinline__ void cand_read_coop(const CandArgs& a, uint64_t r, ui
 // words [8j, 8j + 8) of planes 0..3 in registers and ANDs them with the same
 // words of each candidate bin's vector, and the 4 lanes of a pair sum their
 // counts with DPP moves.
+//
+// NPL is the number of planes a read keeps in LDS: 16, or 8 for reads of at
+// most 255 tokens (no count can reach 256). With 8, a read of more tokens is
+// left to k_cand_long, and a wavefront's LDS halves (4 KB at q = 5), so LDS
+// no longer limits how many wavefronts a CU holds.
 constexpr int kQuadReads = 4;  // reads per wavefront in the quad layout
 
-template <int VW>
+constexpr uint32_t kShortTokens = 255;  // most tokens of a read the 8-plane layout takes
+
+template <int VW, int NPL>
 __device__ __forceinline__ void cand_quad(const CandArgs& a, uint64_t r_first, uint64_t n_reads, uint64_t n_cand,
                                           uint32_t* planes_wave, uint32_t lane) {
   static_assert(VW == 32, "the quad layout is the q = 5 one");
+  static_assert(NPL == 16 || NPL == 8, "planes per read");
   constexpr int WPL = 8, G = VW / WPL, QL = 64 / kQuadReads, PPQ = QL / G, U = G;
-  constexpr uint32_t kPlaneWords = kMaxPlanes * VW;
+  constexpr uint32_t kPlaneWords = NPL * VW;
   const uint32_t qd = lane / QL, ql = lane % QL;
   const uint64_t r = r_first + qd;
   uint32_t* planes = planes_wave + qd * kPlaneWords;
@@ -281,6 +289,7 @@ __device__ __forceinline__ void cand_quad(const CandArgs& a, uint64_t r_first, u
     }
     const int64_t o0 = a.offsets[r];
     if (c1 > c0) ntok = (uint32_t)(a.offsets[r + 1] - o0 - a.q + 1);  // a read without pairs counts nothing
+    if (NPL < kMaxPlanes && ntok > kShortTokens) c0 = c1 = ntok = 0;   // k_cand_long takes it
     tok = a.tokens + token_base(o0, r);
     T = a.thr[r];
   }
@@ -310,8 +319,8 @@ __device__ __forceinline__ void cand_quad(const CandArgs& a, uint64_t r_first, u
       if (old[e] & bit) {
         uint32_t* w = planes + (t >> 5);
         k = 1;
-        // a count stays below 2^16 (at most 65535 tokens), so k stays below kMaxPlanes
-        while ((atomicXor(w + k * VW, bit) & bit) && k + 1 < (uint32_t)kMaxPlanes) ++k;
+        // a count stays below 2^NPL (at most 65535 tokens, or 255 with 8 planes), so k stays below NPL
+        while ((atomicXor(w + k * VW, bit) & bit) && k + 1 < (uint32_t)NPL) ++k;
       }
       top = max(top, k + 1);
     }
@@ -358,9 +367,16 @@ __device__ __forceinline__ void cand_quad(const CandArgs& a, uint64_t r_first, u
     x[1] = (uint32_t)__builtin_amdgcn_mov_dpp((int)xs, 0x55, 0xF, 0xF, false);  // quad_perm 1,1,1,1
     x[2] = (uint32_t)__builtin_amdgcn_mov_dpp((int)xs, 0xAA, 0xF, 0xF, false);  // quad_perm 2,2,2,2
     x[3] = (uint32_t)__builtin_amdgcn_mov_dpp((int)xs, 0xFF, 0xF, 0xF, false);  // quad_perm 3,3,3,3
+    // passes past every quarter's last pair (the short lists' final
+    // iteration) load and count nothing: need[u] is the same in all lanes
+    bool need[U];
+    need[0] = true;
+#pragma unroll
+    for (int u = 1; u < U; ++u) need[u] = __any(npairs - pb > (uint32_t)u * PPQ);
     uint32_t v[U][WPL];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      if (!need[u]) continue;
       const uint4* v4 = reinterpret_cast<const uint4*>(a.bm) + (uint64_t)x[u] * (VW / 4);
 #pragma unroll
       for (int w4 = 0; w4 < WPL / 4; ++w4) {
@@ -371,6 +387,7 @@ __device__ __forceinline__ void cand_quad(const CandArgs& a, uint64_t r_first, u
     uint32_t mine = 0;  // the group's count for pass j
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      if (!need[u]) continue;
       uint32_t part = 0;
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
@@ -404,11 +421,12 @@ __device__ __forceinline__ void cand_quad(const CandArgs& a, uint64_t r_first, u
 
 // LAYOUT: 0 one lane per pair, 1 VW/WPL lanes per pair, 2 four reads per
 // wavefront (q = 5). A wavefront's "step" is one read, or four in layout 2.
-template <int VW, int NW, bool PERSISTENT, int LAYOUT>
+template <int VW, int NW, bool PERSISTENT, int LAYOUT, int NPL>
 __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
-  // one region per wavefront: the multiplicity planes (kMaxPlanes x VW words per read)
+  // one region per wavefront: the multiplicity planes (NPL x VW words per read)
+  static_assert(NPL == kMaxPlanes || LAYOUT == 2, "fewer planes only in the quad layout");
   constexpr uint32_t kReads = LAYOUT == 2 ? kQuadReads : 1;
-  constexpr uint32_t kPerWave = kReads * kMaxPlanes * VW + (LAYOUT == 2 ? kQuadReads : 0);
+  constexpr uint32_t kPerWave = kReads * NPL * VW + (LAYOUT == 2 ? kQuadReads : 0);
   __shared__ __attribute__((aligned(16))) uint32_t lds[NW * kPerWave];
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   uint32_t* planes = lds + wave * kPerWave;
@@ -416,7 +434,7 @@ __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
   const uint64_t n_cand = a.dyn ? min(a.dyn->n_cand, a.n_cand) : a.n_cand;
   if (a.status[0] & ~(uint32_t)(ST_BAD_BIN | ST_BAD_CAND_OFF)) return;  // rejected reads
   auto step = [&](uint64_t r) {
-    if constexpr (LAYOUT == 2) cand_quad<VW>(a, r, n_reads, n_cand, planes, lane);
+    if constexpr (LAYOUT == 2) cand_quad<VW, NPL>(a, r, n_reads, n_cand, planes, lane);
     else if constexpr (LAYOUT == 1) cand_read_coop<VW>(a, r, n_cand, planes, lane);
     else cand_read<VW>(a, r, n_cand, planes, lane);
   };
@@ -438,7 +456,32 @@ __global__ __launch_bounds__(NW * 64) void k_scan_cand(CandArgs a) {
   }
 }
 
-template <int VW, int NW, int LAYOUT>
+// The reads of more than 255 tokens that the 8-plane quad layout leaves: each
+// wavefront looks at 64 reads at a time (a lane each) and runs every long one
+// that has pairs in the cooperative layout with all 16 planes.
+template <int VW>
+__global__ __launch_bounds__(256) void k_cand_long(CandArgs a) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[4 * kMaxPlanes * VW];
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  uint32_t* planes = lds + wave * kMaxPlanes * VW;
+  const uint64_t n_reads = a.dyn ? min(a.dyn->n_reads, a.n_reads) : a.n_reads;
+  const uint64_t n_cand = a.dyn ? min(a.dyn->n_cand, a.n_cand) : a.n_cand;
+  if (a.status[0] & ~(uint32_t)(ST_BAD_BIN | ST_BAD_CAND_OFF)) return;  // rejected reads
+  const uint64_t stride = (uint64_t)gridDim.x * 4 * 64;
+  for (uint64_t base = ((uint64_t)blockIdx.x * 4 + wave) * 64; base < n_reads; base += stride) {
+    const uint64_t r = base + lane;
+    bool is_long = false;
+    if (r < n_reads) is_long = (uint64_t)(a.offsets[r + 1] - a.offsets[r]) > kShortTokens + a.q - 1;
+    uint64_t m = __ballot(is_long);
+    while (m) {
+      const uint32_t l = (uint32_t)__builtin_ctzll(m);
+      m &= m - 1;
+      cand_read_coop<VW>(a, base + l, n_cand, planes, lane);
+    }
+  }
+}
+
+template <int VW, int NW, int LAYOUT, int NPL = kMaxPlanes>
 hipError_t launch_nw_layout(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
   constexpr uint64_t kReads = LAYOUT == 2 ? kQuadReads : 1;
   const bool persistent = cfg.persistent == 1 || (cfg.persistent == 2 && a.n_reads >= kPersistentMinReads);
@@ -455,20 +498,31 @@ hipError_t launch_nw_layout(const CandArgs& a, const CandConfig& cfg, hipStream_
     b.grab = (uint32_t)((grab + kReads - 1) / kReads * kReads);
     hipError_t e = launch_zero_words(a.work, 1, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_scan_cand<VW, NW, true, LAYOUT>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, b);
+    hipLaunchKernelGGL((k_scan_cand<VW, NW, true, LAYOUT, NPL>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, b);
   } else {
     const uint64_t per_block = NW * kReads;
     const uint64_t blocks = (a.n_reads + per_block - 1) / per_block;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_scan_cand<VW, NW, false, LAYOUT>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, a);
+    hipLaunchKernelGGL((k_scan_cand<VW, NW, false, LAYOUT, NPL>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, a);
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if constexpr (NPL < kMaxPlanes) {
+    // reads of more than 255 tokens, left by the 8-plane layout
+    if (e != hipSuccess) return e;
+    const uint64_t groups = std::min<uint64_t>(1024, (a.n_reads + 255) / 256);
+    hipLaunchKernelGGL((k_cand_long<VW>), dim3((unsigned)groups), dim3(256), 0, s, a);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 template <int VW, int NW>
 hipError_t launch_nw(const CandArgs& a, const CandConfig& cfg, hipStream_t s) {
   if constexpr (VW == 32) {
-    if (cfg.coop == 2) return launch_nw_layout<VW, NW, 2>(a, cfg, s);
+    if (cfg.coop == 2) {
+      if (cfg.planes == 16) return launch_nw_layout<VW, NW, 2>(a, cfg, s);
+      return launch_nw_layout<VW, NW, 2, 8>(a, cfg, s);
+    }
   }
   // the cooperative layout needs a pair's vector within one wavefront's lanes
   if constexpr (VW >= 32 && VW <= 512) {

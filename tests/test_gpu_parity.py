@@ -151,6 +151,45 @@ def test_scan_matches_oracle_random(oracle, seed, monkeypatch):
         assert not (m[:, -1] >> (nb % 32)).any()
 
 
+@pytest.mark.parametrize("q,threads,lw", [(5, 1024, 4), (5, 512, 8), (4, 256, 8), (3, 1024, 4), (5, 256, 4)])
+def test_scan_every_remainder(oracle, monkeypatch, q, threads, lw):
+    """Read lengths give every remainder (0..31 tokens) with 0..9 full blocks in
+    one launch, so lanes of one wavefront fold different parts and run
+    different loop counts; a few reads above 255 tokens take the 16-plane path
+    in the same launch. Reads are not length-ordered."""
+    rng = random.Random(1000 * q + threads)
+    B = 32
+    G = B * 2300 + 17
+    ref = rand_ref(rng, G)
+    lens = [q - 1 + 32 * nb + r for nb in range(10) for r in range(32)]  # 32 nb + r tokens
+    lens = [L for L in lens if L >= q] + [300, 290, 260 + q]
+    rng.shuffle(lens)
+    seqs = []
+    for L in lens:
+        p0 = rng.randrange(0, G - L)
+        s = bytearray(ref[p0:p0 + L].tobytes())
+        for _ in range(rng.randrange(0, 4)):
+            if L:
+                s[rng.randrange(L)] = rng.choice(b"ACGTN")
+        seqs.append(bytes(s))
+    rd = synth.reads_from_strings(seqs)
+    me = np.array([rng.randrange(0, 6) for _ in range(rd.n)], np.uint16)
+    monkeypatch.setenv("GRIM_SCAN_THREADS", str(threads))
+    monkeypatch.setenv("GRIM_SCAN_LANE_WORDS", str(lw))
+    monkeypatch.setenv("GRIM_SCAN_CHUNK", str(rng.choice([64, 256])))
+    monkeypatch.setenv("GRIM_SCAN_SORT", "0")
+    idx = build(ref, B, 60, q, grim.LAYOUT_TM)
+    bits = oracle.bits(ref, B, 60, q)
+    nb = bits.shape[0]
+    want_c, want_p = oracle.scan_all(bits, q, rd.bases, rd.offsets, max_edits=me)
+    m, c = gpu_scan(idx, rd, counts_dtype=__import__("torch").uint16, max_edits=me, allow_short_overlap=True)
+    assert np.array_equal(c.astype(np.uint16), want_c)
+    assert np.array_equal(unpack_mask(m, nb), want_p)
+    m2, _ = gpu_scan(idx, rd, max_edits=me, allow_short_overlap=True)
+    assert np.array_equal(m2, m)
+    log("every remainder q", q, "threads", threads, "lane words", lw, "reads", rd.n, "bins", nb)
+
+
 def test_scan_c1_full_size(oracle):
     """The 1 Mbp all-bins workload at its stated size: uint8 counts and pass bits."""
     import torch
@@ -235,6 +274,51 @@ def test_candidates_match_oracle_random(oracle, q, coop, monkeypatch):
     wc, wp = oracle.scan_candidates(bits, q, rd.bases, rd.offsets, co, cb, err_pm_per_read=err)
     assert np.array_equal(host(cnt)[:len(cb)], wc)
     assert np.array_equal(host(pas)[:len(cb)], wp)
+
+
+@pytest.mark.parametrize("planes", [8, 16])
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_candidates_quad_layout_planes(oracle, monkeypatch, planes, persistent):
+    """Four reads per wavefront at q = 5 with 8 or 16 LDS planes per read. Reads
+    above 255 tokens (which the 8-plane form leaves to a second pass over the
+    reads) sit between short ones; homopolymer reads reach counts of 255 (all 8
+    planes) and more; some reads have no pairs."""
+    import torch
+    monkeypatch.setenv("GRIM_CAND_COOP", "2")
+    monkeypatch.setenv("GRIM_CAND_PLANES", str(planes))
+    monkeypatch.setenv("GRIM_CAND_PERSISTENT", str(persistent))
+    rng = random.Random(5150 + planes + persistent)
+    B, O, q = 61, 400, 5
+    ref = rand_ref(rng, 120000)
+    ref[3000:3400] = ord("A")
+    idx = build(ref, B, O, q, grim.LAYOUT_BM)
+    nb = idx.info()["n_bins"]
+    rd = rand_reads(rng, ref, 230, q, 120)
+    extra = [b"A" * 259, b"A" * 260, b"A" * 300, b"C" * 140, ref[3000:3300].tobytes(),
+             rand_reads(rng, ref, 1, 256, 256).bases.tobytes(), rand_reads(rng, ref, 1, 380, 380).bases.tobytes()]
+    strs = [rd.bases[rd.offsets[r]:rd.offsets[r + 1]].tobytes() for r in range(rd.n)]
+    for i, e in enumerate(extra):
+        strs.insert(17 * i + 3, e)
+    rd = synth.reads_from_strings(strs)
+    co, cb = [0], []
+    for r in range(rd.n):
+        k = rng.choice([0, 1, 7, 16, 17, 49, 200])
+        sel = sorted(set(rng.sample(range(nb), min(k, nb))) | ({40, 41, 49} if k else set()))
+        cb += sel
+        co.append(len(cb))
+    co = np.array(co, np.int64)
+    cb = np.array(cb, np.int32)
+    E = np.array([rng.randrange(0, 9) for _ in range(rd.n)], np.uint16)
+    cnt = empty((len(cb),), torch.uint16)
+    pas = empty((len(cb),), torch.uint8)
+    rs = grim.ReadSet(dev(rd.bases), dev(rd.offsets), max_edits=dev(E), allow_short_overlap=True)
+    grim.grim_filter_candidates(idx, rs, dev(co), dev(cb), cnt, pas)
+    bits = oracle.bits(ref, B, O, q)
+    wc, wp = oracle.scan_candidates(bits, q, rd.bases, rd.offsets, co, cb, max_edits=E)
+    assert np.array_equal(host(cnt), wc)
+    assert np.array_equal(host(pas), wp)
+    assert wc.max() >= 255
+    log("quad planes", planes, "persistent", persistent, "reads", rd.n, "pairs", len(cb))
 
 
 def test_candidates_seed_hits_c2_recipe(oracle):
