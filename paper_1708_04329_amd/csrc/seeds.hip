@@ -173,14 +173,22 @@ __global__ __launch_bounds__(256) void k_kmer_fill(const uint8_t* ref, uint64_t 
 }
 
 // Code of the k bases at s, or -1 if one is not A, C, G, T.
+// The k <= 14 bases are all loaded before any is coded (the seed lies within
+// its read), so their latencies overlap.
 __device__ __forceinline__ int64_t seed_code(const uint8_t* s, uint32_t k) {
+  uint8_t b[14];
+#pragma unroll
+  for (uint32_t j = 0; j < 14; ++j) b[j] = j < k ? s[j] : (uint8_t)'A';
   uint64_t code = 0;
-  for (uint32_t j = 0; j < k; ++j) {
-    const int c = base_code(s[j]);
-    if (c < 0) return -1;
-    code = (code << 2) | (uint64_t)c;
+  bool ok = true;
+#pragma unroll
+  for (uint32_t j = 0; j < 14; ++j) {
+    if (j >= k) break;
+    const int c = base_code(b[j]);
+    ok = ok && c >= 0;
+    code = (code << 2) | (uint64_t)(c & 3);
   }
-  return (int64_t)code;
+  return ok ? (int64_t)code : -1;
 }
 
 // A read whose offsets are out of order or outside [0, n_bases] gets no hits
@@ -389,6 +397,44 @@ __device__ void bitonic_sort(uint32_t* d, uint32_t N) {
   }
 }
 
+// Ascending bitonic sort of the 4T values x[] held by a workgroup of T
+// threads, thread t holding elements 4t .. 4t + 3. Partners within a thread
+// are swapped in registers, partners in another lane of the wavefront come
+// by a lane shuffle, and only the stages whose partner is in another
+// wavefront (distance 256 or more) go through LDS (buf, 4T words), with two
+// barriers each: log2(T / 64) (log2(T / 64) + 1) / 2 + ... of the
+// log2(4T) (log2(4T) + 1) / 2 stages, e.g. 3 of 55 for T = 256.
+template <int T>
+__device__ void bitonic_sort_regs(uint32_t (&x)[4], uint32_t* buf) {
+  constexpr uint32_t N = 4 * T;
+  const uint32_t t = threadIdx.x;
+  for (uint32_t k = 2; k <= N; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      uint32_t y[4];
+      if (j >= 256) {
+        __syncthreads();  // every thread is done with buf
+        *reinterpret_cast<uint4*>(buf + 4 * t) = make_uint4(x[0], x[1], x[2], x[3]);
+        __syncthreads();
+        const uint4 v = *reinterpret_cast<const uint4*>(buf + ((4 * t) ^ j));
+        y[0] = v.x; y[1] = v.y; y[2] = v.z; y[3] = v.w;
+      } else if (j >= 4) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) y[e] = (uint32_t)__shfl_xor((int)x[e], (int)(j >> 2));
+      } else if (j == 2) {
+        y[0] = x[2]; y[1] = x[3]; y[2] = x[0]; y[3] = x[1];
+      } else {
+        y[0] = x[1]; y[1] = x[0]; y[2] = x[3]; y[3] = x[2];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t i = 4 * t + (uint32_t)e;
+        const bool take_min = ((i & k) == 0) == ((i & j) == 0);
+        x[e] = take_min ? min(x[e], y[e]) : max(x[e], y[e]);
+      }
+    }
+  }
+}
+
 // Inclusive scan over the 64 lanes of a wavefront.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, uint32_t lane) {
 #pragma unroll
@@ -405,7 +451,7 @@ enum : uint32_t { kModeAll = 0, kModeSelect = 1, kModeFallback = 2 };
 template <int T, int SMAX>
 __global__ __launch_bounds__(T) void k_seed_select(SelArgs a) {
   static_assert(SMAX % T == 0 && T % 64 == 0 && T <= 1024, "shape");
-  __shared__ uint32_t tab[SMAX];
+  __shared__ __attribute__((aligned(16))) uint32_t tab[SMAX];
   __shared__ uint32_t hist[kVoteHist + 1];  // [v]: bins with v votes; [256]: 256 or more
   __shared__ uint32_t dig[256];
   __shared__ uint32_t s_h0[T];
@@ -429,12 +475,16 @@ __global__ __launch_bounds__(T) void k_seed_select(SelArgs a) {
     while (S < (uint32_t)SMAX && room(S) < H) S <<= 1;
     const uint32_t logS = 31u - __clz(S);
     const uint32_t limit = room(S);
-    uint32_t R = 1;
-    if (room(S) < H || a.force_ranges) {
-      R = (uint32_t)min<uint64_t>((H + a.range_hits - 1) / a.range_hits, 1u << 16);
-      if (room(S) < H && R < 2) R = 2;
-      if (R == 0) R = 1;
-    }
+    // A read with more hits than the largest table's room is first tried
+    // whole, counting the slots it claims (its hits often share bins); only
+    // if its distinct bins overflow the table is it taken in ranges.
+    const bool counted = room(S) < H;
+    auto ranges_for = [&]() {
+      uint32_t r = (uint32_t)min<uint64_t>((H + a.range_hits - 1) / a.range_hits, 1u << 16);
+      if (counted && r < 2) r = 2;
+      return r == 0 ? 1u : r;
+    };
+    uint32_t R = a.force_ranges ? ranges_for() : 1u;
 
     auto clear = [&]() {
       __syncthreads();  // every thread is done with the table and the flags
@@ -484,11 +534,105 @@ __global__ __launch_bounds__(T) void k_seed_select(SelArgs a) {
         s_pre[t] = ex;  // threads past the chunk's seeds hold the total
         if (t == 0) s_pre[T] = total;
         __syncthreads();
+        // HB hits per thread at a time: their positions are loaded together,
+        // so the loads' latencies overlap instead of following each insert
+        constexpr uint32_t HB = 8;
         uint32_t s = 0;
-        for (uint32_t f = t; f < total; f += T) {
-          while (s_pre[s + 1] <= f) ++s;
-          const uint32_t bin = hit_bin(a.pos[s_h0[s] + (f - s_pre[s])], (uint64_t)(sc + s) * a.k, a);
-          if (bin >= lo && bin < hi) insert(bin);
+        for (uint32_t f0 = t; f0 < total; f0 += HB * T) {
+          uint32_t p[HB], o[HB];
+#pragma unroll
+          for (uint32_t h = 0; h < HB; ++h) {
+            const uint32_t f = f0 + h * T;
+            p[h] = 0;
+            o[h] = 0;
+            if (f < total) {
+              while (s_pre[s + 1] <= f) ++s;
+              p[h] = a.pos[s_h0[s] + (f - s_pre[s])];
+              o[h] = (sc + s) * a.k;
+            }
+          }
+#pragma unroll
+          for (uint32_t h = 0; h < HB; ++h) {
+            if (f0 + h * T >= total) break;
+            const uint32_t bin = hit_bin(p[h], o[h], a);
+            if (bin >= lo && bin < hi) insert(bin);
+          }
+        }
+        __syncthreads();  // the seed arrays are rewritten by the next chunk
+      }
+      __syncthreads();
+    };
+    // Every hit into the table. Each lane works through its HB hits at its
+    // own pace: one compare-and-swap per probe step, and a lane whose hit is
+    // placed moves on to its next one, so the wavefront does not wait for its
+    // slowest lane's probe chain at every hit. When the read's hits exceed the
+    // table's room (counted), the slots claimed are counted, one atomic per
+    // wavefront and step, and once the count reaches the limit no lane starts
+    // another hit (at most T more slots are claimed, which leaves the table a
+    // free slot, so every probe ends); sh[1] then tells the caller.
+    auto walk_all = [&](bool counted) {
+      for (uint32_t sc = 0; sc < n_seeds; sc += T) {
+        const uint32_t ns = min((uint32_t)T, n_seeds - sc);
+        uint32_t h0 = 0, c = 0;
+        if (t < ns) {
+          const int64_t code = seed_code(rd + (uint64_t)(sc + t) * a.k, a.k);
+          if (code >= 0) {
+            const uint64_t b = a.start[code];
+            h0 = (uint32_t)b;
+            c = (uint32_t)(a.start[code + 1] - b);
+          }
+        }
+        uint32_t total;
+        const uint32_t ex = block_excl_scan<T, uint32_t>(c, ws, &total);
+        s_h0[t] = h0;
+        s_pre[t] = ex;  // threads past the chunk's seeds hold the total
+        if (t == 0) s_pre[T] = total;
+        __syncthreads();
+        constexpr uint32_t HB = 8;
+        uint32_t s = 0;
+        for (uint32_t f0 = t; f0 < total; f0 += HB * T) {
+          uint32_t bins[HB];
+          uint32_t nh = 0;  // this lane's hits in the batch: bins[0 .. nh)
+#pragma unroll
+          for (uint32_t h = 0; h < HB; ++h) {
+            const uint32_t f = f0 + h * T;
+            bins[h] = 0;
+            if (f < total) {
+              while (s_pre[s + 1] <= f) ++s;
+              bins[h] = hit_bin(a.pos[s_h0[s] + (f - s_pre[s])], (uint64_t)(sc + s) * a.k, a);
+              nh = h + 1;
+            }
+          }
+          if (counted && sh[1]) nh = 0;
+          uint32_t bin = bins[0];
+          uint32_t sl = (bin * 0x9E3779B1u) >> (32u - logS);
+          while (nh) {
+            const uint32_t old = atomicCAS(&tab[sl], kEmpty, (bin << a.vb) | 1u);
+            const bool claimed = old == kEmpty;
+            bool placed = claimed;
+            if (!placed && (old >> a.vb) == bin) {
+              const uint32_t o2 = atomicAdd(&tab[sl], 1u);
+              if ((o2 & vmask) + 1u >= vmask) sh[2] = 1u;
+              placed = true;
+            }
+            if (counted) {
+              const uint64_t m = __ballot(claimed);
+              if (m && lane == (uint32_t)__builtin_ctzll(m)) {
+                const uint32_t nc = (uint32_t)__popcll(m);
+                if (atomicAdd(&sh[0], nc) + nc >= limit) sh[1] = 1u;
+              }
+            }
+            if (placed) {
+              --nh;
+#pragma unroll
+              for (uint32_t h = 0; h + 1 < HB; ++h) bins[h] = bins[h + 1];
+              bin = bins[0];
+              sl = (bin * 0x9E3779B1u) >> (32u - logS);
+              if (counted && sh[1]) nh = 0;
+            } else {
+              sl = (sl + 1u) & (S - 1u);
+            }
+          }
         }
         __syncthreads();  // the seed arrays are rewritten by the next chunk
       }
@@ -599,36 +743,48 @@ __global__ __launch_bounds__(T) void k_seed_select(SelArgs a) {
     // the kept entries of the table (all, or more than vt votes plus the ties the rule admits),
     // ascending, to tmp[out_at ..]; returns their number
     auto emit = [&](bool all, uint32_t vt, uint32_t ties, uint32_t bt, uint64_t out_at) -> uint32_t {
-      // compaction to the table's front, CH slots per thread at a time: a
-      // chunk's kept entries land below the chunk's end, in slots already read
-      constexpr uint32_t CH = 4;
-      uint32_t K = 0;
-      for (uint32_t c0 = 0; c0 < S; c0 += CH * T) {
-        uint32_t ev[CH];
-        uint32_t kmask = 0, nk = 0;
+      // every slot of the thread read into registers and tested, one scan for
+      // the kept entries' places, which are then compacted to the table's front
+      constexpr uint32_t SPT = SMAX / T;  // most slots per thread
+      const uint32_t spt = S / T;
+      uint32_t ev[SPT];
+      uint32_t nk = 0;
 #pragma unroll
-        for (uint32_t j = 0; j < CH; ++j) {
-          const uint32_t sl = c0 + j * T + t;
-          const uint32_t e = sl < S ? tab[sl] : kEmpty;
-          ev[j] = e;
+      for (uint32_t u = 0; u < SPT; ++u) {
+        uint32_t e = kEmpty;
+        if (u < spt) {
+          e = tab[u * T + t];
           bool keep = false;
           if (e != kEmpty) {
             const uint32_t v = e & vmask;
-            keep = all || v > vt ||
-                   (v == vt && (ties == kTiesAll || (ties == kTiesUpTo && (e >> a.vb) <= bt)));
+            keep = all || v > vt || (v == vt && (ties == kTiesAll || (ties == kTiesUpTo && (e >> a.vb) <= bt)));
           }
-          kmask |= (uint32_t)keep << j;
-          nk += keep ? 1u : 0u;
+          e = keep ? e >> a.vb : kEmpty;
         }
-        uint32_t chunk;
-        uint32_t p = K + block_excl_scan<T, uint32_t>(nk, ws, &chunk);  // the chunk's reads are done
-#pragma unroll
-        for (uint32_t j = 0; j < CH; ++j)
-          if ((kmask >> j) & 1u) tab[p++] = ev[j] >> a.vb;
-        K += chunk;
+        ev[u] = e;
+        nk += e != kEmpty ? 1u : 0u;
       }
-      const uint32_t N = K <= 1 ? K : 1u << (32 - __clz(K - 1u));
+      uint32_t K;
+      uint32_t p = block_excl_scan<T, uint32_t>(nk, ws, &K);  // every slot has been read
+#pragma unroll
+      for (uint32_t u = 0; u < SPT; ++u)
+        if (ev[u] != kEmpty) tab[p++] = ev[u];
       __syncthreads();
+      if (K <= 4 * T) {
+        // up to four entries per thread: sorted in registers, stored from there
+        uint32_t x[4];
+        const uint4 v = *reinterpret_cast<const uint4*>(tab + 4 * t);
+        x[0] = 4 * t + 0 < K ? v.x : kEmpty;
+        x[1] = 4 * t + 1 < K ? v.y : kEmpty;
+        x[2] = 4 * t + 2 < K ? v.z : kEmpty;
+        x[3] = 4 * t + 3 < K ? v.w : kEmpty;
+        bitonic_sort_regs<T>(x, tab);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (4 * t + (uint32_t)e < K) a.tmp[out_at + 4 * t + e] = x[e];
+        return K;
+      }
+      const uint32_t N = 1u << (32 - __clz(K - 1u));  // K > 4T >= 256
       for (uint32_t q = K + t; q < N; q += T) tab[q] = kEmpty;
       __syncthreads();
       bitonic_sort<T>(tab, N);
@@ -641,8 +797,10 @@ __global__ __launch_bounds__(T) void k_seed_select(SelArgs a) {
     uint32_t kept = 0;
     if (R == 1) {
       clear();
-      walk(0, 0xFFFFFFFFu);
-      if (sh[2]) {
+      walk_all(counted);
+      if (sh[1]) {
+        R = ranges_for();  // its distinct bins overflowed the table
+      } else if (sh[2]) {
         fallback = true;
       } else {
         zero_hist();
@@ -659,7 +817,8 @@ __global__ __launch_bounds__(T) void k_seed_select(SelArgs a) {
           else kept = emit(false, vt, kTiesAll, 0, out0);
         }
       }
-    } else {
+    }
+    if (R > 1) {
       const uint64_t nbins = a.nbins;
       while (true) {
         const uint64_t W = (nbins + R - 1) / R;
@@ -897,6 +1056,13 @@ __global__ __launch_bounds__(256) void k_revcomp(const uint8_t* in, uint64_t n_b
   }
 }
 
+__global__ void k_fill_word(uint32_t* p, uint32_t v) { *p = v; }
+
+hipError_t launch_fill_word(uint32_t* p, uint32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_word, dim3(1), dim3(1), 0, s, p, v);
+  return hipGetLastError();
+}
+
 template <typename T>
 int grow_dev(T** p, uint64_t* cap, uint64_t need) {
   if (*cap >= need && *p) return GRIM_OK;
@@ -941,7 +1107,12 @@ int env_int(const char* name, int dflt) {
 bool env_flag(const char* name) { return env_int(name, 0) != 0; }
 
 // Table size class of a read with h hits (h <= the class's 3/4-full table).
-uint32_t seed_class(uint64_t h) { return h <= 768 ? 0u : h <= 6144 ? 1u : h <= 12288 ? 2u : 3u; }
+// Table sizes (threads, entries): a class's table holds its reads' hits at
+// most 3/4 full; smaller tables leave room for more workgroups per CU.
+constexpr uint32_t kSeedClasses = 6;
+uint32_t seed_class(uint64_t h) {
+  return h <= 768 ? 0u : h <= 1536 ? 1u : h <= 3072 ? 2u : h <= 6144 ? 3u : h <= 12288 ? 4u : 5u;
+}
 
 // n / d for every 32-bit n as (t + ((n - t) >> s1)) >> s2 with t = umulhi(m, n)
 // (the round-up multiplier method of Granlund and Montgomery, 1994).
@@ -1111,7 +1282,7 @@ int grim_seed_candidates(const grim_seeds* csd, const grim_reads* rd, uint32_t b
   uint32_t vb = 32u - key_bits;
   if (const char* e = std::getenv("GRIM_SEED_VOTE_BITS")) vb = std::min<uint32_t>(vb, (uint32_t)std::max(1, std::atoi(e)));
   const bool all_fallback = vb < 2 || env_flag("GRIM_SEED_FALLBACK_ALL");
-  const uint32_t class_min = (uint32_t)std::min(3, std::max(0, env_int("GRIM_SEED_CLASS_MIN", 0)));
+  const uint32_t class_min = (uint32_t)std::min((int)kSeedClasses - 1, std::max(0, env_int("GRIM_SEED_CLASS_MIN", 0)));
   SelArgs a{};
   a.start = sd->start;
   a.pos = sd->pos;
@@ -1127,10 +1298,18 @@ int grim_seed_candidates(const grim_seeds* csd, const grim_reads* rd, uint32_t b
   a.range_hits = (uint32_t)std::max(1, env_int("GRIM_SEED_RANGE_HITS", 16384));
   a.force_ranges = env_flag("GRIM_SEED_FORCE_RANGES") ? 1u : 0u;
   a.n_redo = n_redo;
-  // 2. batches of bounded staging: each read takes min(hits, cap) slots
+  // 2. batches of bounded staging (each read takes min(hits, cap) slots),
+  // planned before anything is launched: every buffer is then allocated
+  // once, each batch's host arrays have a region of their own, and batches
+  // follow each other on the stream with no host wait in between (the host
+  // prepares batch b + 1 while the device runs batch b)
   const uint64_t limit = batch_keys();
-  uint64_t nbatch = 0;
-  for (uint64_t r0 = 0; r0 < n; ++nbatch) {
+  struct Batch {
+    uint64_t r0, r1, slots, max_h;
+  };
+  std::vector<Batch> plan;
+  uint64_t nb_max = 0, slots_max = 1, max_h_all = 0;
+  for (uint64_t r0 = 0; r0 < n;) {
     uint64_t r1 = r0, slots = 0, max_h = 0;
     while (r1 < n && (r1 == r0 || (slots + std::min<uint64_t>(H[r1], cap) <= limit && r1 - r0 < (1ull << 26)))) {
       if (H[r1] > 0xFFFFFFFFull - 64)
@@ -1139,24 +1318,46 @@ int grim_seed_candidates(const grim_seeds* csd, const grim_reads* rd, uint32_t b
       max_h = std::max(max_h, H[r1]);
       ++r1;
     }
-    const uint64_t nb = r1 - r0;
-    // host side: staging offsets and the reads of each launch, grouped by table size
-    if (sd->host_cap < nb) {
-      if (sd->toff_host) (void)hipHostFree(sd->toff_host);
-      if (sd->list_host) (void)hipHostFree(sd->list_host);
-      sd->toff_host = nullptr;
-      sd->list_host = nullptr;
-      sd->host_cap = 0;
-      const uint64_t c = nb + nb / 8 + 64;
-      GRIM_HIP_TRY(hipHostMalloc(&sd->toff_host, c * sizeof(uint64_t), hipHostMallocDefault));
-      GRIM_HIP_TRY(hipHostMalloc(&sd->list_host, c * sizeof(uint32_t), hipHostMallocDefault));
-      sd->host_cap = c;
-    }
-    uint64_t per_class[4] = {0, 0, 0, 0}, n_fb = 0;
+    plan.push_back({r0, r1, slots, max_h});
+    nb_max = std::max(nb_max, r1 - r0);
+    slots_max = std::max(slots_max, slots);
+    max_h_all = std::max(max_h_all, max_h);
+    r0 = r1;
+  }
+  if (sd->host_cap < n) {
+    if (sd->toff_host) (void)hipHostFree(sd->toff_host);
+    if (sd->list_host) (void)hipHostFree(sd->list_host);
+    sd->toff_host = nullptr;
+    sd->list_host = nullptr;
+    sd->host_cap = 0;
+    const uint64_t c = n + n / 8 + 64;
+    GRIM_HIP_TRY(hipHostMalloc(&sd->toff_host, c * sizeof(uint64_t), hipHostMallocDefault));
+    GRIM_HIP_TRY(hipHostMalloc(&sd->list_host, c * sizeof(uint32_t), hipHostMallocDefault));
+    sd->host_cap = c;
+  }
+  const uint64_t np2 = max_h_all <= 1 ? 1 : 1ull << (64 - __builtin_clzll(max_h_all - 1));
+  const uint64_t slab_words = np2 + 2 * max_h_all + 64;
+  const uint64_t fb_waves = std::max<uint64_t>(1, std::min<uint64_t>(512, (128ull << 20) / (slab_words * 4)));
+  if ((rc = grow_dev(&sd->tmp, &sd->tmp_cap, slots_max))) return rc;
+  if ((rc = grow_dev(&sd->toff, &sd->toff_cap, nb_max))) return rc;
+  if ((rc = grow_dev(&sd->outoff, &sd->outoff_cap, nb_max))) return rc;
+  if ((rc = grow_dev(&sd->bsum, &sd->bsum_cap, scan_blocks(nb_max) + 1))) return rc;
+  if ((rc = grow_dev(&sd->cnt, &sd->cnt_cap, nb_max))) return rc;
+  if ((rc = grow_dev(&sd->list, &sd->list_cap, nb_max))) return rc;
+  if ((rc = grow_dev(&sd->redo, &sd->redo_cap, nb_max))) return rc;
+  if ((rc = grow_dev(&sd->slab, &sd->slab_cap, slab_words * fb_waves))) return rc;
+  uint64_t nbatch = 0;
+  for (const Batch& bt : plan) {
+    const uint64_t r0 = bt.r0, nb = bt.r1 - bt.r0;
+    // host side, in this batch's region: staging offsets and the reads of
+    // each launch, grouped by table size
+    uint64_t* toff_h = sd->toff_host + r0;
+    uint32_t* list_h = sd->list_host + r0;
+    uint64_t per_class[kSeedClasses] = {}, n_fb = 0;
     uint64_t run = 0;
     for (uint64_t i = 0; i < nb; ++i) {
       const uint64_t h = H[r0 + i];
-      sd->toff_host[i] = run;
+      toff_h[i] = run;
       run += std::min<uint64_t>(h, cap);
       if (h == 0) continue;
       if (all_fallback) {
@@ -1165,38 +1366,25 @@ int grim_seed_candidates(const grim_seeds* csd, const grim_reads* rd, uint32_t b
       }
       ++per_class[std::max(class_min, seed_class(h))];
     }
-    uint64_t first[5] = {0, 0, 0, 0, 0};
-    for (int c = 0; c < 4; ++c) first[c + 1] = first[c] + per_class[c];
+    uint64_t first[kSeedClasses + 1] = {};
+    for (uint32_t c = 0; c < kSeedClasses; ++c) first[c + 1] = first[c] + per_class[c];
     {
-      uint64_t at[4] = {first[0], first[1], first[2], first[3]};
+      uint64_t at[kSeedClasses];
+      for (uint32_t c = 0; c < kSeedClasses; ++c) at[c] = first[c];
       uint64_t fb = 0;
       for (uint64_t i = 0; i < nb; ++i) {
         const uint64_t h = H[r0 + i];
         if (h == 0) continue;
-        if (all_fallback) sd->list_host[fb++] = (uint32_t)i;
-        else sd->list_host[at[std::max(class_min, seed_class(h))]++] = (uint32_t)i;
+        if (all_fallback) list_h[fb++] = (uint32_t)i;
+        else list_h[at[std::max(class_min, seed_class(h))]++] = (uint32_t)i;
       }
     }
-    const uint64_t listed = all_fallback ? n_fb : first[4];
-    if ((rc = grow_dev(&sd->tmp, &sd->tmp_cap, std::max<uint64_t>(slots, 1)))) return rc;
-    if ((rc = grow_dev(&sd->toff, &sd->toff_cap, nb))) return rc;
-    if ((rc = grow_dev(&sd->outoff, &sd->outoff_cap, nb))) return rc;
-    if ((rc = grow_dev(&sd->bsum, &sd->bsum_cap, scan_blocks(nb) + 1))) return rc;
-    if ((rc = grow_dev(&sd->cnt, &sd->cnt_cap, nb))) return rc;
-    if ((rc = grow_dev(&sd->list, &sd->list_cap, std::max<uint64_t>(listed, 1)))) return rc;
-    if ((rc = grow_dev(&sd->redo, &sd->redo_cap, nb))) return rc;
-    GRIM_HIP_TRY(hipMemcpyAsync(sd->toff, sd->toff_host, nb * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    const uint64_t listed = all_fallback ? n_fb : first[kSeedClasses];
+    GRIM_HIP_TRY(hipMemcpyAsync(sd->toff, toff_h, nb * sizeof(uint64_t), hipMemcpyHostToDevice, s));
     GRIM_HIP_TRY(launch_zero_words(sd->cnt, (uint32_t)nb, s));
-    if (all_fallback) {
-      GRIM_HIP_TRY(hipMemcpyAsync(sd->redo, sd->list_host, std::max<uint64_t>(n_fb, 1) * sizeof(uint32_t),
-                                  hipMemcpyHostToDevice, s));
-      sd->total_host[1] = n_fb;
-      GRIM_HIP_TRY(hipMemcpyAsync(n_redo, sd->total_host + 1, sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    } else {
-      if (listed)
-        GRIM_HIP_TRY(hipMemcpyAsync(sd->list, sd->list_host, listed * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-      GRIM_HIP_TRY(launch_zero_words(n_redo, 1, s));
-    }
+    if (listed) GRIM_HIP_TRY(hipMemcpyAsync(all_fallback ? sd->redo : sd->list, list_h, listed * sizeof(uint32_t),
+                                            hipMemcpyHostToDevice, s));
+    GRIM_HIP_TRY(launch_fill_word(n_redo, all_fallback ? (uint32_t)n_fb : 0u, s));
     a.r0 = r0;
     a.tmp_off = sd->toff;
     a.tmp = sd->tmp;
@@ -1204,7 +1392,7 @@ int grim_seed_candidates(const grim_seeds* csd, const grim_reads* rd, uint32_t b
     a.redo = sd->redo;
     // 3. each read's kept bins, in LDS, one workgroup per read
     if (!all_fallback) {
-      for (int c = 0; c < 4; ++c) {
+      for (uint32_t c = 0; c < kSeedClasses; ++c) {
         if (!per_class[c]) continue;
         SelArgs b = a;
         b.list = sd->list + first[c];
@@ -1212,22 +1400,18 @@ int grim_seed_candidates(const grim_seeds* csd, const grim_reads* rd, uint32_t b
         const dim3 grid((unsigned)std::min<uint64_t>(per_class[c], 1u << 30));
         switch (c) {
           case 0: hipLaunchKernelGGL((k_seed_select<64, 1024>), grid, dim3(64), 0, s, b); break;
-          case 1: hipLaunchKernelGGL((k_seed_select<256, 8192>), grid, dim3(256), 0, s, b); break;
-          case 2: hipLaunchKernelGGL((k_seed_select<512, 16384>), grid, dim3(512), 0, s, b); break;
+          case 1: hipLaunchKernelGGL((k_seed_select<128, 2048>), grid, dim3(128), 0, s, b); break;
+          case 2: hipLaunchKernelGGL((k_seed_select<256, 4096>), grid, dim3(256), 0, s, b); break;
+          case 3: hipLaunchKernelGGL((k_seed_select<256, 8192>), grid, dim3(256), 0, s, b); break;
+          case 4: hipLaunchKernelGGL((k_seed_select<512, 16384>), grid, dim3(512), 0, s, b); break;
           default: hipLaunchKernelGGL((k_seed_select<1024, 32768>), grid, dim3(1024), 0, s, b); break;
         }
         GRIM_HIP_TRY(hipGetLastError());
       }
     }
     // 4. reads the tables could not take (a wavefront each, in device memory)
-    {
-      const uint64_t np2 = max_h <= 1 ? 1 : 1ull << (64 - __builtin_clzll(max_h - 1));
-      const uint64_t slab_words = np2 + 2 * max_h + 64;
-      const uint64_t waves = std::max<uint64_t>(1, std::min<uint64_t>(512, (128ull << 20) / (slab_words * 4)));
-      if ((rc = grow_dev(&sd->slab, &sd->slab_cap, slab_words * waves))) return rc;
-      hipLaunchKernelGGL(k_seed_fallback, dim3((unsigned)waves), dim3(64), 0, s, a, sd->slab, slab_words);
-      GRIM_HIP_TRY(hipGetLastError());
-    }
+    hipLaunchKernelGGL(k_seed_fallback, dim3((unsigned)fb_waves), dim3(64), 0, s, a, sd->slab, slab_words);
+    GRIM_HIP_TRY(hipGetLastError());
     // 5. CSR offsets (continuing the previous batches' total) and the lists in place
     uint64_t* base_in = sd->words + (nbatch & 1);
     uint64_t* base_out = sd->words + ((nbatch + 1) & 1);
@@ -1235,8 +1419,7 @@ int grim_seed_candidates(const grim_seeds* csd, const grim_reads* rd, uint32_t b
     hipLaunchKernelGGL(k_seed_place, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, sd->toff, sd->tmp, sd->cnt,
                        sd->outoff, nb, r0, cand_off, cand_bin);
     GRIM_HIP_TRY(hipGetLastError());
-    GRIM_HIP_TRY(hipStreamSynchronize(s));  // the host arrays are refilled by the next batch
-    r0 = r1;
+    ++nbatch;
   }
   GRIM_HIP_TRY(hipMemcpyAsync(sd->total_host + 2, sd->words + (nbatch & 1), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   GRIM_HIP_TRY(hipStreamSynchronize(s));

@@ -165,9 +165,30 @@ def test_seed_candidates_dense_hits(oracle, k, B, cap):
     log("dense hits k", k, "B", B, "cap", cap, "candidates", len(got[1]))
 
 
+@pytest.mark.parametrize("B,cap", [(8, 40), (8, 30000), (3, 700)])
+def test_seed_candidates_overflowing_tables(oracle, B, cap):
+    """Reads with more hits than the largest table holds are first tried
+    whole. On a 400 kbp genome with 4-mer seeds they have up to ~100K hits;
+    with 8 bp bins (50K bins) or 3 bp bins (133K bins) their distinct bins
+    overflow the table, so they restart in bin ranges, while reads with fewer
+    distinct bins fit; caps below and above the distinct bins."""
+    rng = random.Random(4040 + B + cap)
+    ref = rand_genome(rng, 400_000)
+    seqs = [ref[p:p + L].tobytes() for p, L in ((1000, 250), (70_000, 259), (123_457, 200), (300_000, 64))]
+    rd0 = rand_reads(rng, ref, 60)
+    seqs += [rd0.bases[rd0.offsets[r]:rd0.offsets[r + 1]].tobytes() for r in range(rd0.n)]
+    rd = synth.reads_from_strings(seqs)
+    seeds = grim.grim_seeds_build(dev(ref), 4)
+    got = gpu_candidates(seeds, rd, B, cap)
+    want = oracle.seed_candidates(ref, rd.bases, rd.offsets, 4, B, cap)
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+    log("overflowing tables B", B, "cap", cap, "candidates", len(got[1]))
+
+
 SEED_PATHS = {
-    "largest_table": {"GRIM_SEED_CLASS_MIN": "3"},
-    "bin_ranges": {"GRIM_SEED_CLASS_MIN": "3", "GRIM_SEED_FORCE_RANGES": "1", "GRIM_SEED_RANGE_HITS": "37"},
+    "largest_table": {"GRIM_SEED_CLASS_MIN": "5"},
+    "middle_tables": {"GRIM_SEED_CLASS_MIN": "2"},
+    "bin_ranges": {"GRIM_SEED_CLASS_MIN": "5", "GRIM_SEED_FORCE_RANGES": "1", "GRIM_SEED_RANGE_HITS": "37"},
     "vote_field_full": {"GRIM_SEED_VOTE_BITS": "2"},
     "fallback_only": {"GRIM_SEED_FALLBACK_ALL": "1"},
 }
