@@ -209,6 +209,10 @@ int tokenize_reads(grim_index* idx, const grim_reads* rd, const ReadView& v, uin
   a.flags = rd->flags;
   a.max_tokens = max_tokens;
   a.tok_shift = tok_shift;
+  // plain codes (no shift) serve the candidate and verification calls, which
+  // read a read's entries only up to its token count; the scans' shifted
+  // entries keep the padding their last block reads
+  a.short_pad = tok_shift == 0 ? 1u : 0u;
   a.tokens = ws.tokens;
   a.thr = ws.thr;
   a.status = ws.status;

@@ -95,6 +95,8 @@ struct TokArgs {
   uint32_t flags;
   uint32_t max_tokens;  // 255 when uint8 counts are requested, else 65535
   uint32_t tok_shift;   // tokens are stored as code << tok_shift
+  uint32_t short_pad;   // 1: a read's entries end at the next multiple of 8 (candidate
+                        // checks read no further); 0: past the next multiple of 32 (scans)
   uint32_t* tokens;
   int32_t* thr;
   uint32_t* status;

@@ -123,6 +123,7 @@ extern "C" int grim_filter_candidates_static(const grim_index* cidx, const grim_
   t.flags = rd->flags;
   t.max_tokens = 65535u;
   t.tok_shift = 0;
+  t.short_pad = 1;
   t.tokens = tokens;
   t.thr = thr;
   t.status = status;

@@ -16,7 +16,7 @@
 // as one flat range, eight consecutive tokens per lane and group. Each lane
 // loads the q + 7 bases its eight tokens span, slides a 2q-bit window over
 // them and writes the entries with two 16-byte stores. A read's range is a
-// multiple of 32 tokens, so a group of eight never straddles two reads, and
+// multiple of 8 tokens, so a group of eight never straddles two reads, and
 // every base load lies inside the read (positions past its end count as
 // non-ACGT without a load).
 
@@ -78,8 +78,9 @@ __global__ __launch_bounds__(256) void k_tokenize(TokArgs a) {
       ntok_read = (uint32_t)ntok;
       // padded to the next multiple of 32 strictly above the token count: the
       // scan folds the last partial block exactly and may read one block past
-      // the full ones
-      npad_read = (ntok_read / 32u + 1u) * 32u;
+      // the full ones; candidate checks read whole groups of four up to the
+      // count, so a multiple of 8 serves them
+      npad_read = a.short_pad ? (ntok_read + 7u) & ~7u : (ntok_read / 32u + 1u) * 32u;
     }
   }
 
