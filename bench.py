@@ -47,19 +47,19 @@ MEASURED_TRAFFIC = {
         "sha256": "66e4d61f3b3b448f8d87acb10cf416ec80b72a04997f58219081e8697792cce1",
         "fetch_bytes": 79.8e9, "write_bytes": 190.6e9, "profile": "profiles/k_scan_allbins_c3_3.1Gbp_q5.md"},
     ("c4_candidates_uneven_3.1Gbp_q6", "scan_candidates.hip"): {
-        "sha256": "763061bc871fdca6cf73c1fb9df3103ecdbf196c19ca182f8d8512c35d808dd7",
+        "sha256": "63aa277896ac3793519d0fbd88ea3460caa1ebcb205e7cd64ee2b6448591baa3",
         "fetch_bytes": 1051.7e9, "write_bytes": 13.4e9, "profile": "profiles/k_scan_cand_c4_3.1Gbp_q6.md"},
     ("c2_candidates_100Mbp_q5", "scan_candidates.hip"): {
-        "sha256": "763061bc871fdca6cf73c1fb9df3103ecdbf196c19ca182f8d8512c35d808dd7",
-        "fetch_bytes": 14.45e9, "write_bytes": 1.33e9, "profile": "profiles/k_scan_cand_c2_100Mbp_q5.md"},
+        "sha256": "63aa277896ac3793519d0fbd88ea3460caa1ebcb205e7cd64ee2b6448591baa3",
+        "fetch_bytes": 14.64e9, "write_bytes": 1.50e9, "profile": "profiles/k_scan_cand_c2_100Mbp_q5.md"},
 }
 
 
 # VALU wavefront instructions per launch from rocprofv3 SQ_INSTS_VALU, keyed like the traffic.
 MEASURED_VALU = {
     ("c2_candidates_100Mbp_q5", "scan_candidates.hip"): {
-        "sha256": "763061bc871fdca6cf73c1fb9df3103ecdbf196c19ca182f8d8512c35d808dd7",
-        "valu_wave_insts": 1.0867e9, "profile": "profiles/k_scan_cand_c2_100Mbp_q5.md"},
+        "sha256": "63aa277896ac3793519d0fbd88ea3460caa1ebcb205e7cd64ee2b6448591baa3",
+        "valu_wave_insts": 1.0101e9, "profile": "profiles/k_scan_cand_c2_100Mbp_q5.md"},
 }
 
 
