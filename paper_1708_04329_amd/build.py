@@ -5,6 +5,7 @@
 Each .hip translation unit is compiled in parallel into ``_build/`` and
 linked into ``paper_1708_04329_amd/libgrim.so``, which the Python binding
 loads. The build always recompiles, so a stale library never survives it.
+GRIM_EXTRA_CFLAGS (space-separated) is appended to every hipcc line.
 """
 
 from __future__ import annotations
@@ -30,7 +31,7 @@ CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from forming packed fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function",
+    "-Wall", "-Wno-unused-function", *os.environ.get("GRIM_EXTRA_CFLAGS", "").split(),
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

@@ -213,6 +213,8 @@ int tokenize_reads(grim_index* idx, const grim_reads* rd, const ReadView& v, uin
   // read a read's entries only up to its token count; the scans' shifted
   // entries keep the padding their last block reads
   a.short_pad = tok_shift == 0 ? 1u : 0u;
+  // 128-byte tile rows: the all-bins scan reads tokens in pair order
+  a.pair_order = tok_shift == 7 ? 1u : 0u;
   a.tokens = ws.tokens;
   a.thr = ws.thr;
   a.status = ws.status;

@@ -491,6 +491,7 @@ int build_slot(grim_batcher* b, grim_batch_slot& s) {
     t.max_tokens = 65535u;
     t.tok_shift = cand ? 0u : scan_token_shift(idx->q);
     t.short_pad = cand ? 1u : 0u;
+    t.pair_order = !cand && t.tok_shift == 7 ? 1u : 0u;
     t.tokens = s.d_tokens;
     t.thr = s.d_thr;
     t.status = s.d_status;

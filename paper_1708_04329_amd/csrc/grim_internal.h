@@ -97,6 +97,8 @@ struct TokArgs {
   uint32_t tok_shift;   // tokens are stored as code << tok_shift
   uint32_t short_pad;   // 1: a read's entries end at the next multiple of 8 (candidate
                         // checks read no further); 0: past the next multiple of 32 (scans)
+  uint32_t pair_order;  // 1: order each read's tokens by the parity of their row (the
+                        // all-bins scan with 128-byte tile rows; see launch_tokenize)
   uint32_t* tokens;
   int32_t* thr;
   uint32_t* status;
@@ -196,8 +198,9 @@ struct ScanConfig {
   int sort_by_length = 1;     // process reads longest first (launch_length_order)
 };
 // Sort reads 0..n-1 by their number of 32-token blocks, longest first, into
-// order[]; hist needs length_order_scratch_words() words of scratch. Kernels
-// only (graph-safe).
+// order[]; within a length class, launch position k holds a read whose index
+// has the parity of k while both parities last. hist needs
+// length_order_scratch_words() words of scratch. Kernels only (graph-safe).
 uint64_t length_order_scratch_words();
 hipError_t launch_length_order(const int64_t* offsets, uint64_t n, uint32_t q, const DynSizes* dyn, uint32_t* hist,
                                uint32_t* order, hipStream_t s);

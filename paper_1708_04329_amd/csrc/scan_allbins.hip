@@ -24,7 +24,11 @@
 // tokens then stay in that XCD's L2.
 //
 // Full 32-token blocks go through the Harley-Seal tree, two blocks per step
-// so that only every other block's carry ripples through the upper planes.
+// so that only every other block's carry ripples through the upper planes;
+// their tokens and rows are loaded ahead of use through register rings.
+// Each read's tokens arrive ordered by the parity of their row (see the
+// tokenizer and the length order), so the two reads that share a bank pass
+// of an LDS read take rows in opposite halves of the banks.
 // The remainder of a read is folded first, exactly, as power-of-two parts in
 // increasing size: each part's carry lands in a still-empty plane and needs
 // no ripple, and no padding token costs work unless another read of the
@@ -137,28 +141,70 @@ __device__ __forceinline__ void load_block(uint32_t (&tk)[32], const uint32_t* s
   }
 }
 
-// Fold 32 tokens into the counters.
-template <int LW, int NHI>
-__device__ __forceinline__ void fold32(Counters<LW, NHI>& c, const char* lds_lane, const uint32_t (&tk)[32]) {
-  uint32_t carry[LW];
-  tree<32, LW, NHI>(c, lds_lane, tk, carry);
-  add_carry<5, LW, NHI>(c, carry);
+// Full blocks stream through two rings held in registers. A stretch of 64
+// tokens (two blocks) is folded per loop iteration; chunk j (tokens 4j..4j+3)
+// of the stretch sits in token slot j % 4 and is loaded from global memory
+// three chunks before it is needed, and token i's row sits in row slot i % 4
+// and is read from LDS four tokens before it is needed. Both rings wrap at 64
+// tokens, so the slots line up from one stretch to the next: the last steps
+// of a stretch already load the next stretch's first chunks and rows. Each
+// step ends at a scheduling barrier, which keeps the loads where they are
+// written: two pairs of LDS reads and up to three token chunks stay in flight
+// while a pair of rows is folded, instead of a wait on every pair.
+template <int LW>
+struct Ring {
+  uint32_t tq[4][4];
+  Words<LW> rq[4];
+};
+
+// Load token chunk J of the stretch at `src` (the stretch's first token).
+template <int J, int LW>
+__device__ __forceinline__ void ring_chunk(Ring<LW>& R, const uint32_t* src) {
+  const uint4 v = ldg4(src + 4 * J);
+  R.tq[J % 4][0] = v.x; R.tq[J % 4][1] = v.y; R.tq[J % 4][2] = v.z; R.tq[J % 4][3] = v.w;
+}
+
+// Read token I's row from LDS into its slot.
+template <int I, int LW>
+__device__ __forceinline__ void ring_row(Ring<LW>& R, const char* lds_lane) {
+  R.rq[I % 4] = lds_row<LW>(reinterpret_cast<const uint32_t*>(lds_lane + R.tq[(I / 4) % 4][I % 4]));
+}
+
+// tree<N> over tokens I .. I+N-1 of the stretch, rows taken from the ring.
+template <int N, int I, int LW, int NHI>
+__device__ __forceinline__ void ring_tree(Counters<LW, NHI>& c, Ring<LW>& R, const char* lds_lane,
+                                          const uint32_t* src, uint32_t (&out)[LW]) {
+  if constexpr (N == 2) {
+    if constexpr (I % 4 == 0) ring_chunk<I / 4 + 3, LW>(R, src);
+    const Words<LW> x0 = R.rq[I % 4], x1 = R.rq[(I + 1) % 4];
+#pragma unroll
+    for (int j = 0; j < LW; ++j) CSA(out[j], c.p[0][j], c.p[0][j], x0.w[j], x1.w[j]);
+    ring_row<I + 4, LW>(R, lds_lane);
+    ring_row<I + 5, LW>(R, lds_lane);
+    __builtin_amdgcn_sched_barrier(0);
+  } else {
+    constexpr int L = (N == 4) ? 1 : (N == 8) ? 2 : (N == 16) ? 3 : 4;
+    uint32_t a[LW], b[LW];
+    ring_tree<N / 2, I, LW, NHI>(c, R, lds_lane, src, a);
+    ring_tree<N / 2, I + N / 2, LW, NHI>(c, R, lds_lane, src, b);
+#pragma unroll
+    for (int j = 0; j < LW; ++j) CSA(out[j], c.p[L][j], c.p[L][j], a[j], b[j]);
+  }
 }
 
 // Load N = 2^k token offsets from global memory at `src` (16-byte aligned
-// for N >= 4); lanes that are not active take the all-zero row.
+// for N >= 4).
 template <int N>
-__device__ __forceinline__ void load_part(uint32_t (&tk)[N], const uint32_t* src, bool active, uint32_t zero_off) {
+__device__ __forceinline__ void load_part(uint32_t (&tk)[N], const uint32_t* src) {
   if constexpr (N >= 4) {
 #pragma unroll
     for (int i = 0; i < N / 4; ++i) {
-      uint4 v = make_uint4(zero_off, zero_off, zero_off, zero_off);
-      if (active) v = ldg4(src + 4 * i);
+      const uint4 v = ldg4(src + 4 * i);
       tk[4 * i + 0] = v.x; tk[4 * i + 1] = v.y; tk[4 * i + 2] = v.z; tk[4 * i + 3] = v.w;
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < N; ++i) tk[i] = active ? ldg1(src + i) : zero_off;
+    for (int i = 0; i < N; ++i) tk[i] = ldg1(src + i);
   }
 }
 
@@ -184,77 +230,88 @@ __device__ __forceinline__ void fold_part(Counters<LW, NHI>& c, const char* lds_
 // Threshold test on 32 bit-sliced counters of NP planes: bit b of the result
 // is (counter_b >= T). With K = 2^NP - T the counter reaches T exactly when
 // counter + K carries out of plane NP-1; the carry chain is one majority per
-// plane (km[k] = all-ones when bit k of K is set). T <= 0 passes every bin.
+// plane (km[k] = all-ones when bit k of K is set). T <= 0 passes every bin:
+// then K = 2^NP - 1 with a carry into plane 0 (cin all-ones), so the sum
+// always reaches 2^NP.
 template <int NP>
-__device__ __forceinline__ uint32_t ge_threshold(const uint32_t (&pl)[NP], const uint32_t (&km)[NP],
-                                                 uint32_t allpass) {
-  uint32_t carry = pl[0] & km[0];
+__device__ __forceinline__ uint32_t ge_threshold(const uint32_t (&pl)[NP], const uint32_t (&km)[NP], uint32_t cin) {
+  uint32_t carry = cin;
 #pragma unroll
-  for (int k = 1; k < NP; ++k) carry = maj3(pl[k], km[k], carry);
-  return carry | allpass;
+  for (int k = 0; k < NP; ++k) carry = maj3(pl[k], km[k], carry);
+  return carry;
 }
 
 template <int LW, int NHI, bool COUNTS>
 __device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lane, bool active,
                                           const uint32_t* tok, uint32_t* out_row, uint64_t rid, uint32_t ntok,
-                                          int32_t T, uint64_t gw0, uint32_t zero_off) {
+                                          int32_t T, uint64_t gw0) {
   constexpr int NP = 5 + NHI;
   Counters<LW, NHI> c;
 #pragma unroll
   for (int k = 0; k < NP; ++k)
 #pragma unroll
     for (int j = 0; j < LW; ++j) c.p[k][j] = 0;
-  const uint32_t nfull = active ? ntok >> 5 : 0;
+  // A lane without a read of its own (ntok = 0) streams the tokens of another
+  // read of its chunk and stores nothing, so no load needs a guard.
+  const uint32_t nfull = ntok >> 5;
   // The last partial block first, folded exactly as 1/2/4/8/16-token parts
   // into the empty counters: part 2^k is folded when any lane's remainder
   // has bit k, so the parts cover every lane's remainder, and a lane reads
   // zero-row padding past its own (every token list ends with at least one
   // padding token and is padded to a multiple of 32). The parts' token loads
   // are all issued before the first fold so that their latencies overlap.
-  const uint32_t rem = active ? (ntok & 31u) : 0u;
-  const uint32_t* tail = active ? tok + (uint64_t)nfull * 32 : nullptr;
+  const uint32_t rem = ntok & 31u;
+  const uint32_t* tail = tok + nfull * 32;
   const bool h16 = __any(rem & 16u), h8 = __any(rem & 8u), h4 = __any(rem & 4u), h2 = __any(rem & 2u),
              h1 = __any(rem & 1u);
   const uint32_t p8 = h16 ? 16 : 0, p4 = p8 + (h8 ? 8 : 0), p2 = p4 + (h4 ? 4 : 0), p1 = p2 + (h2 ? 2 : 0);
   uint32_t t16[16], t8[8], t4[4], t2[2], t1[1];
-  if (h16) load_part<16>(t16, tail, active, zero_off);
-  if (h8) load_part<8>(t8, tail + p8, active, zero_off);
-  if (h4) load_part<4>(t4, tail + p4, active, zero_off);
-  if (h2) load_part<2>(t2, tail + p2, active, zero_off);
-  if (h1) load_part<1>(t1, tail + p1, active, zero_off);
+  if (h16) load_part<16>(t16, tail);
+  if (h8) load_part<8>(t8, tail + p8);
+  if (h4) load_part<4>(t4, tail + p4);
+  if (h2) load_part<2>(t2, tail + p2);
+  if (h1) load_part<1>(t1, tail + p1);
   if (h1) fold_part<1, LW, NHI>(c, lds_lane, t1);
   if (h2) fold_part<2, LW, NHI>(c, lds_lane, t2);
   if (h4) fold_part<4, LW, NHI>(c, lds_lane, t4);
   if (h8) fold_part<8, LW, NHI>(c, lds_lane, t8);
   if (h16) fold_part<16, LW, NHI>(c, lds_lane, t16);
-  // full 32-token blocks, two at a time: the weight-32 carries of the two
-  // trees meet in one full adder at plane 5, and only its carry ripples on
+  // An odd full block goes next, as a part of 32: the count is still below 32,
+  // so its weight-32 carry becomes plane 5. Then the remaining full blocks,
+  // two at a time: the weight-32 carries of the two trees meet in one full
+  // adder at plane 5, and only its carry ripples on.
   uint32_t b = 0;
-  for (; b + 2 <= nfull; b += 2) {
-    uint32_t c1[LW], c2[LW], c64[LW];
-    {
-      uint32_t tk[32];
-      load_block(tk, tok + b * 32);
-      tree<32, LW, NHI>(c, lds_lane, tk, c1);
-    }
-    {
-      uint32_t tk[32];
-      load_block(tk, tok + (b + 1) * 32);
-      tree<32, LW, NHI>(c, lds_lane, tk, c2);
-    }
+  if (nfull & 1u) {
+    uint32_t tk[32], c32[LW];
+    load_block(tk, tok);
+    tree<32, LW, NHI>(c, lds_lane, tk, c32);
 #pragma unroll
-    for (int j = 0; j < LW; ++j) CSA(c64[j], c.p[5][j], c.p[5][j], c1[j], c2[j]);
-    add_carry<6, LW, NHI>(c, c64);
+    for (int j = 0; j < LW; ++j) c.p[5][j] = c32[j];
+    b = 1;
   }
-  if (b < nfull) {
-    uint32_t tk[32];
-    load_block(tk, tok + b * 32);
-    fold32<LW, NHI>(c, lds_lane, tk);
+  if (b + 2 <= nfull) {
+    Ring<LW> R;
+    const uint32_t* src = tok + b * 32;
+    ring_chunk<0, LW>(R, src);
+    ring_chunk<1, LW>(R, src);
+    ring_chunk<2, LW>(R, src);
+    ring_row<0, LW>(R, lds_lane);
+    ring_row<1, LW>(R, lds_lane);
+    ring_row<2, LW>(R, lds_lane);
+    ring_row<3, LW>(R, lds_lane);
+    for (; b + 2 <= nfull; b += 2, src += 64) {
+      uint32_t c1[LW], c2[LW], c64[LW];
+      ring_tree<32, 0, LW, NHI>(c, R, lds_lane, src, c1);
+      ring_tree<32, 32, LW, NHI>(c, R, lds_lane, src, c2);
+#pragma unroll
+      for (int j = 0; j < LW; ++j) CSA(c64[j], c.p[5][j], c.p[5][j], c1[j], c2[j]);
+      add_carry<6, LW, NHI>(c, c64);
+    }
   }
   if (!active) return;
   // K = 2^NP - T as NP all-ones/all-zeros masks, shared by the lane's words
-  const uint32_t allpass = T <= 0 ? 0xFFFFFFFFu : 0u;
-  const uint32_t K = T <= 0 ? 0u : (uint32_t)((1u << NP) - (uint32_t)T);
+  const uint32_t cin = T <= 0 ? 0xFFFFFFFFu : 0u;
+  const uint32_t K = T <= 0 ? (1u << NP) - 1u : (uint32_t)((1u << NP) - (uint32_t)T);
   uint32_t km[NP];
 #pragma unroll
   for (int k = 0; k < NP; ++k) km[k] = ((K >> k) & 1u) ? 0xFFFFFFFFu : 0u;
@@ -266,7 +323,7 @@ __device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lan
       uint32_t pl[NP];
 #pragma unroll
       for (int k = 0; k < NP; ++k) pl[k] = c.p[k][j];
-      o[j] = ge_threshold<NP>(pl, km, allpass);
+      o[j] = ge_threshold<NP>(pl, km, cin);
     }
     return;
   }
@@ -277,7 +334,7 @@ __device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lan
     uint32_t pl[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) pl[k] = c.p[k][j];
-    uint32_t ge = ge_threshold<NP>(pl, km, allpass);
+    uint32_t ge = ge_threshold<NP>(pl, km, cin);
     if (gw == a.W - 1 && (a.nb & 31)) ge &= (1u << (a.nb & 31)) - 1u;
     out_row[gw] = ge;
     if (COUNTS && a.counts_out) {
@@ -337,45 +394,45 @@ __global__ __launch_bounds__(NT) void k_scan_allbins(ScanArgs a) {
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const uint32_t g = lane / G, s = lane % G;
   const char* lds_lane = reinterpret_cast<const char*>(lds) + s * LW * 4;
-  const uint32_t zero_off = R4 * TW * 4;  // byte offset of the all-zero row
   const uint64_t gw0 = (uint64_t)tile * TW + (uint64_t)s * LW;
   const uint64_t r_begin = (uint64_t)rchunk * a.reads_per_chunk;
   uint64_t r_end = r_begin + a.reads_per_chunk;
   if (r_end > n_reads) r_end = n_reads;
 
   for (uint64_t base = r_begin + (uint64_t)wave * RPW; base < r_end; base += (uint64_t)NW * RPW) {
-    const uint64_t k = base + g;
-    const bool active = k < r_end;
-    uint64_t rid = 0;
-    const uint32_t* tok = nullptr;
-    uint32_t* out_row = nullptr;
-    uint32_t ntok = 0;
-    int32_t T = 0;
-    if (active) {
-      rid = a.read_order ? a.read_order[k] : k;
-      if (a.desc) {
-        const ReadDesc d = a.desc[rid];
-        tok = d.tok;
-        out_row = d.out;
-        ntok = d.ntok;
-        T = d.T;
-      } else {
-        const int64_t o0 = a.offsets[rid], o1 = a.offsets[rid + 1];
-        ntok = (uint32_t)(o1 - o0 - a.q + 1);
-        tok = a.tokens + token_base(o0, rid);
-        out_row = a.mask_out + rid * a.W;
-        T = a.thr[rid];
-      }
+    const uint64_t k0 = base + g;
+    const bool active = k0 < r_end;
+    // a lane past the chunk's end takes the chunk's first read (always
+    // present) with no tokens of its own; it stores nothing
+    const uint64_t k = active ? k0 : r_begin;
+    const uint64_t rid = a.read_order ? a.read_order[k] : k;
+    const uint32_t* tok;
+    uint32_t* out_row;
+    uint32_t ntok;
+    int32_t T;
+    if (a.desc) {
+      const ReadDesc d = a.desc[rid];
+      tok = d.tok;
+      out_row = d.out;
+      ntok = d.ntok;
+      T = d.T;
+    } else {
+      const int64_t o0 = a.offsets[rid], o1 = a.offsets[rid + 1];
+      ntok = (uint32_t)(o1 - o0 - a.q + 1);
+      tok = a.tokens + token_base(o0, rid);
+      out_row = a.mask_out + rid * a.W;
+      T = a.thr[rid];
     }
+    if (!active) ntok = 0;
     if (__any(ntok > 255)) {
       // 16 counter planes: two (or one) words per pass keeps the registers
       // of this rare path within the budget of the common one
       constexpr int LWW = LW >= 2 ? 2 : 1;
 #pragma unroll
       for (int h = 0; h < LW / LWW; ++h)
-        scan_read<LWW, 11, COUNTS>(a, lds_lane + h * LWW * 4, active, tok, out_row, rid, ntok, T, gw0 + h * LWW, zero_off);
+        scan_read<LWW, 11, COUNTS>(a, lds_lane + h * LWW * 4, active, tok, out_row, rid, ntok, T, gw0 + h * LWW);
     } else {
-      scan_read<LW, 3, COUNTS>(a, lds_lane, active, tok, out_row, rid, ntok, T, gw0, zero_off);
+      scan_read<LW, 3, COUNTS>(a, lds_lane, active, tok, out_row, rid, ntok, T, gw0);
     }
   }
 }

@@ -153,6 +153,49 @@ __global__ __launch_bounds__(256) void k_tokenize(TokArgs a) {
   }
 }
 
+// Token order for the all-bins scan's LDS reads. The sum over a read's tokens
+// does not depend on their order, so each read's tokens are reordered in
+// place: those whose tile row has the read index's parity first, the others
+// after, each class in its original order. The scan's launch order puts a read
+// of even index beside one of odd index (the length order alternates them),
+// and the two share the bank pass of every LDS read: one takes a row of even
+// index where the other takes a row of odd index for all but about
+// |evens(a) - odds(b)| token positions, and rows of opposite parity lie in
+// different halves of the LDS banks (128-byte rows). One wavefront per read;
+// reads of more than 256 tokens keep the sequence order.
+__global__ __launch_bounds__(256) void k_pair_order(TokArgs a) {
+  const uint64_t r = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
+  const uint64_t n_reads = a.dyn ? min(a.dyn->n_reads, a.n_reads) : a.n_reads;
+  const uint64_t n_bases = a.dyn ? min(a.dyn->n_bases, a.n_bases) : a.n_bases;
+  if (r >= n_reads) return;
+  const int64_t o0 = a.offsets[r], o1 = a.offsets[r + 1];
+  // the tokenizer flagged reads with bad offsets or lengths and wrote no entries
+  if (o0 < 0 || o1 < o0 || (uint64_t)o1 > n_bases || o1 - o0 < (int64_t)a.q) return;
+  const uint64_t ntok = (uint64_t)(o1 - o0) - a.q + 1;
+  if (ntok > 256) return;
+  uint32_t* t = a.tokens + token_base(o0, r);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t want = (uint32_t)(r & 1u);
+  const uint64_t lt = (1ull << lane) - 1ull;
+  uint32_t v[4], first_before[4];
+  bool first[4];
+  uint32_t nfirst = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t p = lane + 64u * j;
+    v[j] = p < ntok ? t[p] : 0u;
+    first[j] = p < ntok && ((v[j] >> a.tok_shift) & 1u) == want;
+    const uint64_t bal = __ballot(first[j]);
+    first_before[j] = nfirst + (uint32_t)__popcll(bal & lt);
+    nfirst += (uint32_t)__popcll(bal);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t p = lane + 64u * j;
+    if (p < ntok) t[first[j] ? first_before[j] : nfirst + (p - first_before[j])] = v[j];
+  }
+}
+
 }  // namespace
 
 // With a.dyn set, a.n_reads / a.n_bases are the capacities the grid is sized for.
@@ -175,6 +218,11 @@ hipError_t launch_tokenize(const TokArgs& a, hipStream_t s) {
     case 8: hipLaunchKernelGGL(k_tokenize<8>, grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !a.pair_order) return e;
+  const uint64_t pblocks = (a.n_reads + 3) / 4;
+  if (pblocks > 0x7FFFFFFFull) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_pair_order, dim3((unsigned)pblocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
