@@ -31,11 +31,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "read×bin checks/s (bit-exact) + served reads/s & p99 latency vs plain launch"
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 int32 lane-ops/s.
+# MI355X: 256 CUs x 4 SIMDs at 2.4 GHz. A SIMD issues up to two wave64 VALU
+# instructions every 4 cycles (from two waves; rocprof's SQ_ACTIVE_INST_VALU2
+# counts those cycles), i.e. 32 lane-ops per cycle: 7.86e13 int32 lane-ops/s,
+# the same rate that gives the 157.3 TFLOP/s fp32 vector peak (FMA = 2 flops).
 # A full adder on 32 bins is two lane-ops (v_bitop3 xor3 + majority), so one
 # lane-op advances at most 16 bit-accumulations.
-ALU_LANE_OPS = 256 * 64 * 2.4e9
+ALU_LANE_OPS = 256 * 4 * 32 * 2.4e9
 BITACC_PEAK = ALU_LANE_OPS * 32 / 2
+# LDS reads: 256 bytes per cycle per CU on gfx950 (ds_read_b128 without bank
+# conflicts). The all-bins scan reads one index bit from LDS per
+# bit-accumulation, so its LDS ceiling equals its ALU ceiling.
+LDS_PEAK = 256 * 256 * 2.4e9
 HBM_PEAK = 8.0e12
 MALL_BYTES = 256 << 20  # Infinity Cache
 
@@ -44,8 +51,8 @@ MALL_BYTES = 256 << 20  # Infinity Cache
 # they were taken on; reported as null once the source has changed since.
 MEASURED_TRAFFIC = {
     ("c3_allbins_3.1Gbp_q5", "scan_allbins.hip"): {
-        "sha256": "66e4d61f3b3b448f8d87acb10cf416ec80b72a04997f58219081e8697792cce1",
-        "fetch_bytes": 79.8e9, "write_bytes": 190.6e9, "profile": "profiles/k_scan_allbins_c3_3.1Gbp_q5.md"},
+        "sha256": "109201eba2124d4496a91d3adfa5d753001230ff6f0d1855021aed32924ee729",
+        "fetch_bytes": 80.95e9, "write_bytes": 190.70e9, "profile": "profiles/k_scan_allbins_c3_3.1Gbp_q5.md"},
     ("c4_candidates_uneven_3.1Gbp_q6", "scan_candidates.hip"): {
         "sha256": "63aa277896ac3793519d0fbd88ea3460caa1ebcb205e7cd64ee2b6448591baa3",
         "fetch_bytes": 1051.7e9, "write_bytes": 13.4e9, "profile": "profiles/k_scan_cand_c4_3.1Gbp_q6.md"},
@@ -259,12 +266,18 @@ def main():
                     "traffic": measured_traffic(w.name, "scan_allbins.hip"),
                     "kernel": "k_scan_allbins", "avg_launch_ms": avg_ms,
                     "work_per_launch": f"{work_units:.4g} bit-accumulations (tokens x bins)"}
+        lds_bytes = work_units / 8
+        roofline["lds"] = {"achieved_GB_per_s": lds_bytes / (avg_ms * 1e-3) / 1e9, "peak_GB_per_s": LDS_PEAK / 1e9,
+                           "frac": lds_bytes / (avg_ms * 1e-3) / LDS_PEAK,
+                           "note": "one index bit read from LDS per bit-accumulation (16 B per lane and token for "
+                                   "128 bins); this ceiling coincides with the ALU one"}
         # the stated HBM goal for the full-genome scan (0.60 of peak) is not met:
-        # the kernel is bound by VALU issue, and its HBM rate is what that leaves
+        # the kernel works from LDS-staged tiles, and its HBM rate is what that leaves
         tr = roofline["traffic"]
         roofline["hbm_goal"] = {"target_frac": 0.60, "met": False,
                                 "measured_frac": None if tr is None else tr / (avg_ms * 1e-3) / HBM_PEAK,
-                                "note": "bound by VALU issue (full adders per token-word), not HBM"}
+                                "note": "the index is read from HBM once per read chunk and tile; the kernel is "
+                                        "bound by VALU issue and LDS reads at 4 waves per SIMD, not by HBM"}
     elif info["bm_bytes"] > MALL_BYTES:
         # the gathered vectors cannot all stay in the 256 MB Infinity Cache; the
         # counters (L2 misses) cannot tell Infinity Cache hits from HBM reads, so
