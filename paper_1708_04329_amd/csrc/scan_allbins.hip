@@ -91,31 +91,6 @@ struct Counters {
   uint32_t p[5 + NHI][LW];
 };
 
-// Carry-save tree over N = 2^k tokens (tk[i] = LDS byte offset of token i's
-// row): the tokens' rows are folded into planes 0..k-1 and the carry of
-// weight N is returned in out[]. tree<32> is Harley-Seal over a 32-token block:
-// 31 full adders per word.
-template <int N, int LW, int NHI>
-__device__ __forceinline__ void tree(Counters<LW, NHI>& c, const char* lds_lane, const uint32_t* tk,
-                                     uint32_t (&out)[LW]) {
-  if constexpr (N == 2) {
-    const Words<LW> x0 = lds_row<LW>(reinterpret_cast<const uint32_t*>(lds_lane + tk[0]));
-    const Words<LW> x1 = lds_row<LW>(reinterpret_cast<const uint32_t*>(lds_lane + tk[1]));
-#pragma unroll
-    for (int j = 0; j < LW; ++j) CSA(out[j], c.p[0][j], c.p[0][j], x0.w[j], x1.w[j]);
-  } else {
-    constexpr int L = (N == 4) ? 1 : (N == 8) ? 2 : (N == 16) ? 3 : 4;  // level of the two halves' carries
-    uint32_t a[LW], b[LW];
-    tree<N / 2, LW, NHI>(c, lds_lane, tk, a);
-    tree<N / 2, LW, NHI>(c, lds_lane, tk + N / 2, b);
-#pragma unroll
-    for (int j = 0; j < LW; ++j) CSA(out[j], c.p[L][j], c.p[L][j], a[j], b[j]);
-    // keep the scheduler from hoisting later LDS loads above this point: with
-    // 8 words per lane, 32 tokens of loads in flight would not fit the VGPRs
-    if constexpr (LW >= 8 && N == 8) __builtin_amdgcn_sched_barrier(0);
-  }
-}
-
 // Add a carry of weight 2^L (one bit per bin) to the counters: half adders up
 // through planes L..4, then the binary planes of weight 32 and up.
 template <int L, int LW, int NHI>
@@ -177,8 +152,11 @@ __device__ __forceinline__ void ring_tree(Counters<LW, NHI>& c, Ring<LW>& R, con
   if constexpr (N == 2) {
     if constexpr (I % 4 == 0) ring_chunk<I / 4 + 3, LW>(R, src);
     const Words<LW> x0 = R.rq[I % 4], x1 = R.rq[(I + 1) % 4];
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int j = 0; j < LW; ++j) CSA(out[j], c.p[0][j], c.p[0][j], x0.w[j], x1.w[j]);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_setprio(0);
     ring_row<I + 4, LW>(R, lds_lane);
     ring_row<I + 5, LW>(R, lds_lane);
     __builtin_amdgcn_sched_barrier(0);
@@ -187,8 +165,11 @@ __device__ __forceinline__ void ring_tree(Counters<LW, NHI>& c, Ring<LW>& R, con
     uint32_t a[LW], b[LW];
     ring_tree<N / 2, I, LW, NHI>(c, R, lds_lane, src, a);
     ring_tree<N / 2, I + N / 2, LW, NHI>(c, R, lds_lane, src, b);
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int j = 0; j < LW; ++j) CSA(out[j], c.p[L][j], c.p[L][j], a[j], b[j]);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_setprio(0);
   }
 }
 
@@ -208,20 +189,63 @@ __device__ __forceinline__ void load_part(uint32_t (&tk)[N], const uint32_t* src
   }
 }
 
-// Fold N = 2^k tokens of a read's remainder into the counters. Parts are
-// folded first, in increasing size, so before part 2^k the count is at most
-// 1 + 2 + ... + 2^(k-1) < 2^k: plane k and every plane above it are still
-// zero, and the tree's carry of weight 2^k simply becomes plane k (no ripple).
+// The remainder parts and an odd full block take their tokens from registers
+// (loaded together before the first fold) and their rows through a ring of
+// four, read from LDS four tokens ahead, as in the block loop.
+template <int LW>
+struct Rows {
+  Words<LW> rq[4];
+};
+
+template <int I, int N, int LW>
+__device__ __forceinline__ void part_row(Rows<LW>& R, const char* lds_lane, const uint32_t* tk) {
+  if constexpr (I < N) R.rq[I % 4] = lds_row<LW>(reinterpret_cast<const uint32_t*>(lds_lane + tk[I]));
+}
+
+// tree<M> over tokens I .. I+M-1 of an N-token part, rows from the ring.
+template <int M, int I, int N, int LW, int NHI>
+__device__ __forceinline__ void part_tree(Counters<LW, NHI>& c, Rows<LW>& R, const char* lds_lane, const uint32_t* tk,
+                                          uint32_t (&out)[LW]) {
+  if constexpr (M == 2) {
+    const Words<LW> x0 = R.rq[I % 4], x1 = R.rq[(I + 1) % 4];
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int j = 0; j < LW; ++j) CSA(out[j], c.p[0][j], c.p[0][j], x0.w[j], x1.w[j]);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_setprio(0);
+    part_row<I + 4, N, LW>(R, lds_lane, tk);
+    part_row<I + 5, N, LW>(R, lds_lane, tk);
+    __builtin_amdgcn_sched_barrier(0);
+  } else {
+    constexpr int L = (M == 4) ? 1 : (M == 8) ? 2 : (M == 16) ? 3 : 4;
+    uint32_t a[LW], b[LW];
+    part_tree<M / 2, I, N, LW, NHI>(c, R, lds_lane, tk, a);
+    part_tree<M / 2, I + M / 2, N, LW, NHI>(c, R, lds_lane, tk, b);
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int j = 0; j < LW; ++j) CSA(out[j], c.p[L][j], c.p[L][j], a[j], b[j]);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_setprio(0);
+  }
+}
+
+// Fold N = 2^k tokens into the counters, whose planes k and up are still
+// zero; the tree's carry of weight 2^k becomes plane k.
 template <int N, int LW, int NHI>
-__device__ __forceinline__ void fold_part(Counters<LW, NHI>& c, const char* lds_lane, const uint32_t (&tk)[N]) {
-  constexpr int L = (N == 1) ? 0 : (N == 2) ? 1 : (N == 4) ? 2 : (N == 8) ? 3 : 4;
+__device__ __forceinline__ void fold_into_empty(Counters<LW, NHI>& c, const char* lds_lane, const uint32_t (&tk)[N]) {
+  constexpr int L = (N == 1) ? 0 : (N == 2) ? 1 : (N == 4) ? 2 : (N == 8) ? 3 : (N == 16) ? 4 : 5;
   if constexpr (N == 1) {
     const Words<LW> x = lds_row<LW>(reinterpret_cast<const uint32_t*>(lds_lane + tk[0]));
 #pragma unroll
     for (int j = 0; j < LW; ++j) c.p[0][j] = x.w[j];
   } else {
+    Rows<LW> R;
+    part_row<0, N, LW>(R, lds_lane, tk);
+    part_row<1, N, LW>(R, lds_lane, tk);
+    part_row<2, N, LW>(R, lds_lane, tk);
+    part_row<3, N, LW>(R, lds_lane, tk);
     uint32_t carry[LW];
-    tree<N, LW, NHI>(c, lds_lane, tk, carry);
+    part_tree<N, 0, N, LW, NHI>(c, R, lds_lane, tk, carry);
 #pragma unroll
     for (int j = 0; j < LW; ++j) c.p[L][j] = carry[j];
   }
@@ -271,22 +295,20 @@ __device__ __forceinline__ void scan_read(const ScanArgs& a, const char* lds_lan
   if (h4) load_part<4>(t4, tail + p4);
   if (h2) load_part<2>(t2, tail + p2);
   if (h1) load_part<1>(t1, tail + p1);
-  if (h1) fold_part<1, LW, NHI>(c, lds_lane, t1);
-  if (h2) fold_part<2, LW, NHI>(c, lds_lane, t2);
-  if (h4) fold_part<4, LW, NHI>(c, lds_lane, t4);
-  if (h8) fold_part<8, LW, NHI>(c, lds_lane, t8);
-  if (h16) fold_part<16, LW, NHI>(c, lds_lane, t16);
+  if (h1) fold_into_empty<1, LW, NHI>(c, lds_lane, t1);
+  if (h2) fold_into_empty<2, LW, NHI>(c, lds_lane, t2);
+  if (h4) fold_into_empty<4, LW, NHI>(c, lds_lane, t4);
+  if (h8) fold_into_empty<8, LW, NHI>(c, lds_lane, t8);
+  if (h16) fold_into_empty<16, LW, NHI>(c, lds_lane, t16);
   // An odd full block goes next, as a part of 32: the count is still below 32,
   // so its weight-32 carry becomes plane 5. Then the remaining full blocks,
   // two at a time: the weight-32 carries of the two trees meet in one full
   // adder at plane 5, and only its carry ripples on.
   uint32_t b = 0;
   if (nfull & 1u) {
-    uint32_t tk[32], c32[LW];
+    uint32_t tk[32];
     load_block(tk, tok);
-    tree<32, LW, NHI>(c, lds_lane, tk, c32);
-#pragma unroll
-    for (int j = 0; j < LW; ++j) c.p[5][j] = c32[j];
+    fold_into_empty<32, LW, NHI>(c, lds_lane, tk);
     b = 1;
   }
   if (b + 2 <= nfull) {
