@@ -265,7 +265,9 @@ def main():
                     "unit": "Tbit-acc/s", "frac": achieved / BITACC_PEAK,
                     "traffic": measured_traffic(w.name, "scan_allbins.hip"),
                     "kernel": "k_scan_allbins", "avg_launch_ms": avg_ms,
-                    "work_per_launch": f"{work_units:.4g} bit-accumulations (tokens x bins)"}
+                    "work_per_launch": f"{work_units:.4g} bit-accumulations (tokens x bins)",
+                    "peak_basis": "256 CUs x 4 SIMDs x 32 lane-ops per cycle (two wave64 VALU instructions "
+                                  "per SIMD per 4 cycles) x 2.4 GHz x 16 bit-accumulations per lane-op"}
         lds_bytes = work_units / 8
         roofline["lds"] = {"achieved_GB_per_s": lds_bytes / (avg_ms * 1e-3) / 1e9, "peak_GB_per_s": LDS_PEAK / 1e9,
                            "frac": lds_bytes / (avg_ms * 1e-3) / LDS_PEAK,
