@@ -62,6 +62,33 @@ def test_c3_full_size(oracle, human_genome):
     log("c3 pass rate in sample", float(want.mean()))
 
 
+def test_c3_full_size_mixed_thresholds(oracle, human_genome):
+    """The same 1M x 150 bp reads and launch shape with E drawn from 0..7 per read: at q = 5 most
+    of a 2 kbp bin's tokens are present, so E = 7 passes nearly every bin and small E rejects
+    most; sampled rows of both kinds bit-exact against the oracle."""
+    import torch
+    w = C.workload("c3")
+    ref = human_genome
+    rd = synth.reads(w.reads, ref)
+    idx = grim.grim_build_index(dev(ref), w.bin_size, w.overlap, w.q, grim.LAYOUT_TM)
+    nb, W = idx.info()["n_bins"], idx.info()["mask_words"]
+    E = np.random.default_rng(57).integers(0, w.max_edits + 1, size=rd.n).astype(np.uint16)
+    mask = empty((rd.n, W), torch.uint32)
+    grim.grim_filter_scan(idx, grim.ReadSet(dev(rd.bases), dev(rd.offsets), max_edits=dev(E)), mask)
+    torch.cuda.synchronize()
+    ids = np.sort(np.random.default_rng(59).choice(rd.n, size=256, replace=False))
+    got = host(mask.view(torch.int32)[torch.from_numpy(ids).cuda()]).view(np.uint32)
+    del mask
+    torch.cuda.empty_cache()
+    bits = oracle.bits(ref, w.bin_size, w.overlap, w.q)
+    sub = rd.subset(ids)
+    _, want = oracle.scan_all(bits, w.q, sub.bases, sub.offsets, max_edits=E[ids], want_counts=False)
+    assert np.array_equal(unpack_mask(got, nb), want)
+    rate = float(want.mean())
+    log("c3 mixed-E pass rate in sample", rate)
+    assert 0.1 < rate < 0.9, rate  # both outcomes well represented
+
+
 def test_c4_full_size(oracle, human_genome):
     """2M uneven reads, 2,048,000,000 candidate pairs: sampled reads bit-exact, listed truth bins pass."""
     import torch
