@@ -18,6 +18,7 @@ namespace grim {
 namespace {
 
 constexpr int kSumThreads = 256;
+constexpr int kBatch = 4;  // 16-byte loads in flight per thread
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -45,8 +46,23 @@ __global__ __launch_bounds__(kSumThreads) void k_mask_summary(const uint32_t* ma
     uint64_t dg = 0;
     if (t < head) add_word(t, row[t], pc, dg);
     const uint4* body = reinterpret_cast<const uint4*>(row + head);
-#pragma unroll 4
-    for (uint64_t k = t; k < n4; k += kSumThreads) {
+    // kBatch 16-byte loads per thread are issued before any is used, so
+    // enough bytes are in flight per CU to cover the memory latency
+    uint64_t k = t;
+    for (; k + (kBatch - 1) * kSumThreads < n4; k += kBatch * kSumThreads) {
+      uint4 v[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) v[b] = body[k + b * kSumThreads];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const uint64_t i = head + 4 * (k + b * kSumThreads);
+        add_word(i, v[b].x, pc, dg);
+        add_word(i + 1, v[b].y, pc, dg);
+        add_word(i + 2, v[b].z, pc, dg);
+        add_word(i + 3, v[b].w, pc, dg);
+      }
+    }
+    for (; k < n4; k += kSumThreads) {
       const uint4 v = body[k];
       const uint64_t i = head + 4 * k;
       add_word(i, v.x, pc, dg);
