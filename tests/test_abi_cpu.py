@@ -211,3 +211,13 @@ def test_bench_refuses_more_than_one_gpu():
     p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=300)
     assert p.returncode == 2 and "exactly one GPU" in p.stderr
+
+
+def test_probes_build_for_gfx950():
+    """The microbenchmarks behind the scan's stated ceilings compile (hipcc cross-compiles here)."""
+    import shutil
+    if not os.path.exists(os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")) and not shutil.which("hipcc"):
+        pytest.skip("hipcc is not installed")
+    from paper_1708_04329_amd.probes import run
+    exe = run.build()
+    assert os.path.getsize(exe) > 0
