@@ -183,9 +183,8 @@ struct ScanArgs {
   const int32_t* thr;
   const uint32_t* read_order;  // chunk position -> read index, or null for identity
   uint64_t n_reads;
-  uint32_t reads_per_chunk;
   uint32_t n_tiles;
-  uint32_t n_rchunks;
+  uint32_t n_rchunks;          // read chunks (set by the launcher): a multiple of 8
   uint32_t* mask_out;
   void* counts_out;
   uint32_t counts_bytes;
@@ -193,7 +192,7 @@ struct ScanArgs {
 };
 struct ScanConfig {
   int threads = 1024;         // threads per workgroup (16 waves: 4 per SIMD)
-  int reads_per_chunk = 4096; // reads per workgroup
+  int reads_per_chunk = 4096; // reads per workgroup (at most)
   int lane_words = 4;         // uint32 words (x32 bins) per lane: 4 or 8
   int sort_by_length = 1;     // process reads longest first (launch_length_order)
 };

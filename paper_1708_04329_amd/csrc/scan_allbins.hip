@@ -21,7 +21,8 @@
 // loads per token. Tokens arrive pre-scaled to the LDS byte offset of their
 // row, so a row address costs one add per token. Workgroup ids are remapped
 // so the 32 CUs of one XCD work on the tiles of the same read chunk, whose
-// tokens then stay in that XCD's L2.
+// tokens then stay in that XCD's L2; chunks go round-robin to the XCDs, and
+// their number is a multiple of 8, so each XCD gets the same work.
 //
 // Full 32-token blocks go through the Harley-Seal tree, two blocks per step
 // so that only every other block's carry ripples through the upper planes;
@@ -389,7 +390,18 @@ __global__ __launch_bounds__(NT) void k_scan_allbins(ScanArgs a) {
   const uint32_t rchunk = rc_local * 8u + xcd;
   if (rchunk >= a.n_rchunks) return;
   const uint64_t n_reads = a.dyn ? min(a.dyn->n_reads, a.n_reads) : a.n_reads;
-  if ((uint64_t)rchunk * a.reads_per_chunk >= n_reads) return;
+  // The reads' workgroup iterations are dealt out evenly over the chunks
+  // (sizes differ by at most one iteration); with a chunk count that is a
+  // multiple of 8, every XCD gets the same share of the work.
+  constexpr uint32_t kIter = (uint32_t)(NW * RPW);
+  const uint64_t n_iter = (n_reads + kIter - 1) / kIter;
+  const uint64_t per = n_iter / a.n_rchunks, extra = n_iter % a.n_rchunks;
+  const uint64_t it0 = (uint64_t)rchunk * per + min((uint64_t)rchunk, extra);
+  const uint64_t its = per + (rchunk < extra ? 1 : 0);
+  const uint64_t r_begin = it0 * kIter;
+  uint64_t r_end = r_begin + its * kIter;
+  if (r_end > n_reads) r_end = n_reads;
+  if (r_begin >= r_end) return;
   if (a.status && a.status[0] != 0) return;  // inputs were rejected: leave outputs untouched
 
   // stage the tile: rows 0..R4-1 from HBM, row R4 = zeros
@@ -417,9 +429,6 @@ __global__ __launch_bounds__(NT) void k_scan_allbins(ScanArgs a) {
   const uint32_t g = lane / G, s = lane % G;
   const char* lds_lane = reinterpret_cast<const char*>(lds) + s * LW * 4;
   const uint64_t gw0 = (uint64_t)tile * TW + (uint64_t)s * LW;
-  const uint64_t r_begin = (uint64_t)rchunk * a.reads_per_chunk;
-  uint64_t r_end = r_begin + a.reads_per_chunk;
-  if (r_end > n_reads) r_end = n_reads;
 
   for (uint64_t base = r_begin + (uint64_t)wave * RPW; base < r_end; base += (uint64_t)NW * RPW) {
     const uint64_t k0 = base + g;
@@ -460,8 +469,15 @@ __global__ __launch_bounds__(NT) void k_scan_allbins(ScanArgs a) {
 }
 
 template <int TW, int LW, int NT>
-hipError_t launch_t(const ScanArgs& a, hipStream_t s) {
-  const uint64_t per_xcd = (a.n_rchunks + 7) / 8;
+hipError_t launch_t(ScanArgs a, uint64_t reads_per_chunk, hipStream_t s) {
+  // chunks of at most reads_per_chunk reads (whole workgroup iterations of
+  // NT / (TW / LW) reads), as many per XCD on each of the 8 XCDs
+  constexpr uint64_t kIter = (uint64_t)NT / (TW / LW);
+  const uint64_t n_iter = (a.n_reads + kIter - 1) / kIter;
+  const uint64_t it_per_chunk = reads_per_chunk / kIter > 0 ? reads_per_chunk / kIter : 1;
+  const uint64_t per_xcd = (n_iter + 8 * it_per_chunk - 1) / (8 * it_per_chunk);
+  if (per_xcd > 0x0FFFFFFFull) return hipErrorInvalidConfiguration;
+  a.n_rchunks = (uint32_t)(8 * per_xcd);
   const uint64_t blocks = 8ull * per_xcd * a.n_tiles;
   if (blocks == 0) return hipSuccess;
   if (blocks > 0x7FFFFFFFull) return hipErrorInvalidConfiguration;
@@ -480,17 +496,16 @@ hipError_t launch_t(const ScanArgs& a, hipStream_t s) {
 hipError_t launch_scan_allbins(const ScanArgs& a0, const ScanConfig& cfg, hipStream_t s) {
   ScanArgs a = a0;
   const int TW = tm_tile_words(a.q);
-  a.reads_per_chunk = (uint32_t)cfg.reads_per_chunk;
+  const uint64_t rpc = cfg.reads_per_chunk > 0 ? (uint64_t)cfg.reads_per_chunk : 1;
   a.n_tiles = (uint32_t)((a.W + TW - 1) / TW);
-  a.n_rchunks = (uint32_t)((a.n_reads + a.reads_per_chunk - 1) / a.reads_per_chunk);
   if (a.n_reads == 0 || a.n_tiles == 0) return hipSuccess;
   const int nt = cfg.threads;
   const bool w8 = cfg.lane_words == 8;
 #define GRIM_SCAN_NT(TW_, LW_)                                              \
   do {                                                                      \
-    if (nt == 1024) return launch_t<TW_, LW_, 1024>(a, s);                  \
-    if (nt == 256) return launch_t<TW_, LW_, 256>(a, s);                    \
-    return launch_t<TW_, LW_, 512>(a, s);                                   \
+    if (nt == 1024) return launch_t<TW_, LW_, 1024>(a, rpc, s);             \
+    if (nt == 256) return launch_t<TW_, LW_, 256>(a, rpc, s);               \
+    return launch_t<TW_, LW_, 512>(a, rpc, s);                              \
   } while (0)
   switch (TW) {
     case 32:
