@@ -92,7 +92,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
-    p.add_argument("--serve-seconds", type=float, default=60.0,
+    p.add_argument("--serve-seconds", type=float, default=30.0,
                    help="all-bins workloads: also replay this many seconds of the Poisson request stream through "
                         "the continuous server (0 = skip), and its first --plain-serve-seconds through the plain one")
     p.add_argument("--reads-scale", type=float, default=1.0, help="fraction of the stated read count (testing only)")
@@ -107,9 +107,14 @@ def parse():
     p.add_argument("--no-verify", action="store_true",
                    help="candidate workloads: skip aligning the passing pairs after the filter")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
+    p.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of the serving leg (requests/s)")
+    p.add_argument("--serve-heavy-rate", type=float, default=800.0,
+                   help="arrival rate of a second serving leg near the continuous server's capacity (0 = skip); "
+                        "both servers replay --serve-heavy-seconds of it")
+    p.add_argument("--serve-heavy-seconds", type=float, default=20.0)
     p.add_argument("--plain-serve-seconds", type=float, default=20.0,
-                   help="seconds of the same request stream replayed through the plain server (it saturates "
-                        "below the offered load, so its latency grows with the replay's length)")
+                   help="seconds of the same request stream replayed through the plain server (above its "
+                        "capacity it falls behind, and its latency grows with the replay's length)")
     p.add_argument("--batch-reads", type=int, default=16384,
                    help="all-bins workloads: reads per batch of the batching-layer leg (0 = skip)")
     p.add_argument("--batch-replays", type=int, default=50, help="batches per slot in the batching-layer leg")
@@ -363,7 +368,11 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
     if w.mode == "allbins" and args.serve_seconds > 0:
-        out["serving"] = serving(args, ref, idx, info)
+        out["serving"] = serving(args, ref, idx, info, args.serve_rate, args.serve_seconds,
+                                 min(args.serve_seconds, args.plain_serve_seconds))
+        if args.serve_heavy_rate > 0 and args.serve_heavy_seconds > 0:
+            out["serving_heavy"] = serving(args, ref, idx, info, args.serve_heavy_rate, args.serve_heavy_seconds,
+                                           args.serve_heavy_seconds)
         if args.workload == "c5":
             sv = out["serving"]
             out["config"]["workload"] = "c5_serving_3.1Gbp_q5"
@@ -371,6 +380,12 @@ def main():
                                    "p99_ms": sv["continuous"]["p99_ms"],
                                    "plain_reads_per_s": sv["plain"]["reads_per_s"],
                                    "plain_p99_ms": sv["plain"]["p99_ms"]}
+            if "serving_heavy" in out:
+                hv = out["serving_heavy"]
+                out["metric_parts"].update({"heavy_served_reads_per_s": hv["continuous"]["reads_per_s"],
+                                            "heavy_p99_ms": hv["continuous"]["p99_ms"],
+                                            "heavy_plain_reads_per_s": hv["plain"]["reads_per_s"],
+                                            "heavy_plain_p99_ms": hv["plain"]["p99_ms"]})
     print(json.dumps(out), flush=True)
 
 
@@ -718,8 +733,9 @@ def request_stream(seconds: float, rate: float, pool_n: int, seed: int, size_max
     return out
 
 
-def serving(args, ref, idx, info):
-    """Replay one seeded request stream through the continuous and the plain server."""
+def serving(args, ref, idx, info, rate, seconds, plain_seconds):
+    """Replay one seeded request stream (Poisson arrivals at `rate` per second) through the
+    continuous server for `seconds` and its first `plain_seconds` through the plain one."""
     import ctypes
     import threading
     import synth
@@ -731,7 +747,7 @@ def serving(args, ref, idx, info):
     spec.n_reads = pool_n
     t0 = time.time()
     pool = synth.reads(spec, ref)
-    stream = request_stream(args.serve_seconds, 200.0, pool_n, seed=w5.reads.seed + 17)
+    stream = request_stream(seconds, rate, pool_n, seed=w5.reads.seed + 17)
     reqs = []
     for (ta, start, n) in stream:
         o0 = int(pool.offsets[start])
@@ -740,8 +756,8 @@ def serving(args, ref, idx, info):
         reqs.append((ta, grim.ReadSet(bases, np.ascontiguousarray(offs),
                                       err_permille=np.ascontiguousarray(pool.err_pm[start:start + n].astype(np.uint16))),
                      start, n))
-    offered = sum(r[3] for r in reqs) / args.serve_seconds
-    log(f"serving: {len(reqs)} requests over {args.serve_seconds:.0f}s, {offered:,.0f} reads/s offered "
+    offered = sum(r[3] for r in reqs) / seconds
+    log(f"serving: {len(reqs)} requests over {seconds:.0f}s at {rate:g}/s, {offered:,.0f} reads/s offered "
         f"(pool built in {time.time() - t0:.1f}s)")
     hip = ctypes.CDLL("libamdhip64.so")
     hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
@@ -749,8 +765,7 @@ def serving(args, ref, idx, info):
     results = {}
     all_reqs = reqs
     for name, policy in (("continuous", grim.SERVE_CONTINUOUS), ("plain", grim.SERVE_PLAIN)):
-        span = args.serve_seconds if policy == grim.SERVE_CONTINUOUS else min(args.serve_seconds,
-                                                                               args.plain_serve_seconds)
+        span = seconds if policy == grim.SERVE_CONTINUOUS else plain_seconds
         reqs = [r for r in all_reqs if r[0] < span]
         srv = grim.Server(idx, policy, reserve_bytes=8 << 30, max_inflight=256, max_request_reads=20000)
         tickets = [None] * len(reqs)
@@ -817,8 +832,9 @@ def serving(args, ref, idx, info):
             f"p99 {st['p99_ms']:.2f} ms, {st['launches']} launches, exact {exact[0]}")
     results["offered_reads_per_s"] = offered
     results["requests"] = len(all_reqs)
-    results["seconds"] = args.serve_seconds
-    results["arrivals"] = "Poisson 200 req/s, log-uniform 1..20000 reads of 100/150/250 bp (30/40/30), e in 2..5%"
+    results["seconds"] = seconds
+    results["arrivals"] = (f"Poisson {rate:g} req/s, log-uniform 1..20000 reads of 100/150/250 bp "
+                           "(30/40/30), e in 2..5%")
     return results
 
 
