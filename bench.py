@@ -92,7 +92,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
-    p.add_argument("--serve-seconds", type=float, default=30.0,
+    p.add_argument("--serve-seconds", type=float, default=60.0,
                    help="all-bins workloads: also replay this many seconds of the Poisson request stream through "
                         "the continuous server (0 = skip), and its first --plain-serve-seconds through the plain one")
     p.add_argument("--reads-scale", type=float, default=1.0, help="fraction of the stated read count (testing only)")
