@@ -445,8 +445,8 @@ typedef struct grim_server grim_server;
 typedef struct {
   uint32_t policy;            /* GRIM_SERVE_CONTINUOUS or GRIM_SERVE_PLAIN */
   uint32_t max_inflight;      /* admitted requests at once (0: 64) */
-  uint32_t max_batch_reads;   /* reads per launch, continuous policy (0: 65536) */
-  uint32_t slice_reads;       /* reads one request adds to a launch (0: 16384) */
+  uint32_t max_batch_reads;   /* reads per launch, continuous policy (0: 131072) */
+  uint32_t slice_reads;       /* reads one request adds to a launch (0: 32768) */
   uint32_t n_streams;         /* device streams for launches (0: 2; plain: 1) */
   uint32_t max_request_reads; /* largest request accepted (0: 65536) */
   uint64_t arena_bytes;       /* device bytes the server serves from (0: free HBM - reserve_bytes) */

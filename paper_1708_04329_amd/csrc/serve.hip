@@ -543,8 +543,8 @@ extern "C" int grim_serve_create(const grim_index* idx, const grim_serve_config*
   if (c.policy > GRIM_SERVE_PLAIN) return set_error(GRIM_EINVAL, "bad policy");
   if (c.flags & ~GRIM_READS_ALLOW_SHORT_OVERLAP) return set_error(GRIM_EINVAL, "unknown flags");
   if (!c.max_inflight) c.max_inflight = 64;
-  if (!c.max_batch_reads) c.max_batch_reads = 65536;
-  if (!c.slice_reads) c.slice_reads = 16384;
+  if (!c.max_batch_reads) c.max_batch_reads = 131072;
+  if (!c.slice_reads) c.slice_reads = 32768;
   if (!c.n_streams) c.n_streams = 2;
   if (!c.max_request_reads) c.max_request_reads = 65536;
   if (!c.host_arena_bytes) c.host_arena_bytes = 1ull << 30;
