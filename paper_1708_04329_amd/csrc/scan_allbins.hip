@@ -423,6 +423,11 @@ __global__ __launch_bounds__(NT) void k_scan_allbins(ScanArgs a) {
     }
   }
   for (uint32_t i = threadIdx.x; i < TW; i += NT) lds[R4 * TW + i] = 0;
+  // groups of RPW reads go to the wavefronts in order of demand: each takes
+  // group `wave` first, then the next unclaimed one, so the workgroup ends
+  // when its last group ends rather than with its slowest wavefront's share
+  __shared__ uint32_t next_group;
+  if (threadIdx.x == 0) next_group = NW;
   __syncthreads();
 
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
@@ -430,7 +435,9 @@ __global__ __launch_bounds__(NT) void k_scan_allbins(ScanArgs a) {
   const char* lds_lane = reinterpret_cast<const char*>(lds) + s * LW * 4;
   const uint64_t gw0 = (uint64_t)tile * TW + (uint64_t)s * LW;
 
-  for (uint64_t base = r_begin + (uint64_t)wave * RPW; base < r_end; base += (uint64_t)NW * RPW) {
+  const uint64_t n_groups = (r_end - r_begin + RPW - 1) / RPW;
+  for (uint32_t grp = wave; grp < n_groups;) {
+    const uint64_t base = r_begin + (uint64_t)grp * RPW;
     const uint64_t k0 = base + g;
     const bool active = k0 < r_end;
     // a lane past the chunk's end takes the chunk's first read (always
@@ -465,6 +472,9 @@ __global__ __launch_bounds__(NT) void k_scan_allbins(ScanArgs a) {
     } else {
       scan_read<LW, 3, COUNTS>(a, lds_lane, active, tok, out_row, rid, ntok, T, gw0);
     }
+    uint32_t claim = 0;
+    if (lane == 0) claim = atomicAdd(&next_group, 1u);
+    grp = (uint32_t)__builtin_amdgcn_readlane((int)claim, 0);
   }
 }
 
