@@ -153,11 +153,9 @@ __device__ __forceinline__ void ring_tree(Counters<LW, NHI>& c, Ring<LW>& R, con
   if constexpr (N == 2) {
     if constexpr (I % 4 == 0) ring_chunk<I / 4 + 3, LW>(R, src);
     const Words<LW> x0 = R.rq[I % 4], x1 = R.rq[(I + 1) % 4];
-    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int j = 0; j < LW; ++j) CSA(out[j], c.p[0][j], c.p[0][j], x0.w[j], x1.w[j]);
     __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_setprio(0);
     ring_row<I + 4, LW>(R, lds_lane);
     ring_row<I + 5, LW>(R, lds_lane);
     __builtin_amdgcn_sched_barrier(0);
@@ -166,11 +164,9 @@ __device__ __forceinline__ void ring_tree(Counters<LW, NHI>& c, Ring<LW>& R, con
     uint32_t a[LW], b[LW];
     ring_tree<N / 2, I, LW, NHI>(c, R, lds_lane, src, a);
     ring_tree<N / 2, I + N / 2, LW, NHI>(c, R, lds_lane, src, b);
-    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int j = 0; j < LW; ++j) CSA(out[j], c.p[L][j], c.p[L][j], a[j], b[j]);
     __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_setprio(0);
   }
 }
 
@@ -209,11 +205,9 @@ __device__ __forceinline__ void part_tree(Counters<LW, NHI>& c, Rows<LW>& R, con
                                           uint32_t (&out)[LW]) {
   if constexpr (M == 2) {
     const Words<LW> x0 = R.rq[I % 4], x1 = R.rq[(I + 1) % 4];
-    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int j = 0; j < LW; ++j) CSA(out[j], c.p[0][j], c.p[0][j], x0.w[j], x1.w[j]);
     __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_setprio(0);
     part_row<I + 4, N, LW>(R, lds_lane, tk);
     part_row<I + 5, N, LW>(R, lds_lane, tk);
     __builtin_amdgcn_sched_barrier(0);
@@ -222,11 +216,9 @@ __device__ __forceinline__ void part_tree(Counters<LW, NHI>& c, Rows<LW>& R, con
     uint32_t a[LW], b[LW];
     part_tree<M / 2, I, N, LW, NHI>(c, R, lds_lane, tk, a);
     part_tree<M / 2, I + M / 2, N, LW, NHI>(c, R, lds_lane, tk, b);
-    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int j = 0; j < LW; ++j) CSA(out[j], c.p[L][j], c.p[L][j], a[j], b[j]);
     __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_setprio(0);
   }
 }
 
