@@ -166,7 +166,6 @@ __device__ __forceinline__ void ring_tree(Counters<LW, NHI>& c, Ring<LW>& R, con
     ring_tree<N / 2, I + N / 2, LW, NHI>(c, R, lds_lane, src, b);
 #pragma unroll
     for (int j = 0; j < LW; ++j) CSA(out[j], c.p[L][j], c.p[L][j], a[j], b[j]);
-    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -218,7 +217,6 @@ __device__ __forceinline__ void part_tree(Counters<LW, NHI>& c, Rows<LW>& R, con
     part_tree<M / 2, I + M / 2, N, LW, NHI>(c, R, lds_lane, tk, b);
 #pragma unroll
     for (int j = 0; j < LW; ++j) CSA(out[j], c.p[L][j], c.p[L][j], a[j], b[j]);
-    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
