@@ -51,8 +51,8 @@ MALL_BYTES = 256 << 20  # Infinity Cache
 # they were taken on; reported as null once the source has changed since.
 MEASURED_TRAFFIC = {
     ("c3_allbins_3.1Gbp_q5", "scan_allbins.hip"): {
-        "sha256": "47a59f7b61f7144936ce79bb068d1b63e45de6867b50f2e0465f1b7a80a0ad4e",
-        "fetch_bytes": 83.25e9, "write_bytes": 190.85e9, "profile": "profiles/k_scan_allbins_c3_3.1Gbp_q5.md"},
+        "sha256": "677b3ca8d1abe2a7620437dd65688d1c9b251ecf6e8ae2ce5aa4a0356e67ba4a",
+        "fetch_bytes": 83.10e9, "write_bytes": 192.09e9, "profile": "profiles/k_scan_allbins_c3_3.1Gbp_q5.md"},
     ("c4_candidates_uneven_3.1Gbp_q6", "scan_candidates.hip"): {
         "sha256": "63aa277896ac3793519d0fbd88ea3460caa1ebcb205e7cd64ee2b6448591baa3",
         "fetch_bytes": 1051.7e9, "write_bytes": 13.4e9, "profile": "profiles/k_scan_cand_c4_3.1Gbp_q6.md"},
