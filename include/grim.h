@@ -338,7 +338,9 @@ int grim_reverse_complement(const uint8_t* bases, uint64_t n_bases, const int64_
 typedef struct {
   uint32_t mode;               /* GRIM_MODE_* the fields below apply to */
   uint32_t threads;            /* all-bins: threads per workgroup (256, 512, 1024) */
-  uint32_t reads_per_chunk;    /* all-bins: reads per workgroup, i.e. per LDS tile reuse (>= 64) */
+  uint32_t reads_per_chunk;    /* all-bins: most reads per workgroup, i.e. per LDS tile reuse (>= 64); the
+                                  launcher deals the reads evenly over a multiple of 8 chunks of at most
+                                  this many */
   uint32_t lane_words;         /* all-bins: uint32 words = 32-bin groups per lane (4 or 8) */
   uint32_t cand_waves;         /* candidates: wavefronts per workgroup (0 = by vector size) */
   uint32_t cand_persistent;    /* candidates: 1 = fixed grid with reads handed out by an atomic
