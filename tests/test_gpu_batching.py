@@ -215,6 +215,39 @@ def test_batcher_scan_every_replay_matches_eager(oracle):
     b.free()
 
 
+def test_batcher_scan_many_chunks_smaller_replays(oracle):
+    """A capture for 40000 reads cuts them into 16 read chunks (two per XCD). Replays of fewer
+    reads deal their workgroup iterations over the same chunks, some of which then stay empty;
+    every replay must equal the eager call, and sampled rows the oracle."""
+    import torch
+    w = C.shrink(C.workload("c3"), genome_len=3_000_000, n_reads=40000)
+    ref = synth.genome(w.genome)
+    rd = synth.reads(w.reads, ref)
+    idx = grim.grim_build_index(dev(ref), w.bin_size, w.overlap, w.q, grim.LAYOUT_TM)
+    W = idx.info()["mask_words"]
+    nb = idx.info()["n_bins"]
+    bits = oracle.bits(ref, w.bin_size, w.overlap, w.q)
+    b = grim.Batcher(idx, grim.MODE_SCAN, max_reads=40000, max_bases=40000 * 150, edits_kind=grim.BATCH_EDITS_NONE,
+                     err_permille_all=45)
+    for it, n in enumerate([40000, 12345, 129, 40000, 2047]):
+        slot = it % 2
+        ids = np.arange(n)
+        buf = b.buffers(slot)
+        sub, nbases, _ = _fill_batch(buf, rd, ids)
+        log("many-chunk replay", it, "reads", n)
+        b.submit(slot, n, nbases)
+        b.wait(slot)
+        got = d2h(buf["mask_out_device"], n * W * 4).view(np.uint32).reshape(n, W)
+        m = empty((n, W), torch.uint32)
+        grim.grim_filter_scan(idx, grim.ReadSet(dev(sub.bases), dev(sub.offsets), err_permille_all=45), m)
+        assert np.array_equal(got, host(m)), it
+        rows = np.unique(np.concatenate([np.arange(0, n, max(1, n // 40)), [n - 1]]))
+        sr = sub.subset(rows)
+        _, wp = oracle.scan_all(bits, w.q, sr.bases, sr.offsets, err_permille=45, want_counts=False)
+        assert np.array_equal(unpack_mask(got[rows], nb), wp), it
+    b.free()
+
+
 def test_batcher_errors(uneven):
     w, ref, rd, co, cb, idx = uneven
     b = grim.Batcher(idx, grim.MODE_CANDIDATES, max_reads=10, max_bases=3000, max_cand=100)
